@@ -1,0 +1,747 @@
+/*
+ * Plain, sequential FP64 CPU oracle of the fluctuating two-component D3Q19
+ * lattice Boltzmann step with one moving, wettable, finite-size sphere.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the CPU
+ * baseline of the benchmark.  The HIP product path never includes, links or
+ * calls it, and it includes nothing of the product.
+ *
+ * Paper: Xue, Biferale, Sbragaglia, Toschi, "A lattice Boltzmann study of
+ * particle settling in a fluctuating multicomponent fluid under confinement".
+ *   Sec. 2, eq. (density)      moments rho_l, rho_tot v
+ *   Sec. 2, eq. (lbe)          stream + collide + deterministic source + noise
+ *   Sec. 2, MRT paragraph      modes relaxed separately; momentum-mode rate
+ *                              sets D, stress-mode rate sets eta
+ *   Sec. 2, eq. (sc-force)     Shan-Chen inter-component force
+ *   Sec. 2, noise paragraph    no noise on mass, FDT noise on the other modes;
+ *                              hydrodynamic velocity v + (F_A+F_B)/(2 rho_tot)
+ *   Sec. 2, particle paragraph particle nodes, leap-frog Newton, moving
+ *                              bounce-back with momentum exchange, cover /
+ *                              uncover, global mass correction, virtual
+ *                              wetting layer (+Delta rho)
+ *   Sec. 3, eq. (fp)           external force on the particle
+ *   Sec. 4, Langevin paragraph particle mass m_p = pi d^3 rho_p / 6
+ * Where the paper is silent the readings listed in the design notes are
+ * used (basis, forcing scheme, noise layout, generator, event rules).
+ *
+ * Every loop is written in the order of the method; nothing is fused or
+ * blocked.  Compile with -ffp-contract=off: the particle-node predicate must
+ * round identically on every implementation.
+ */
+#include "lbm_oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* ---------------------------------------------------------------- lattice */
+/* D3Q19: rest, 6 axis links (+,- pairs), 12 planar diagonals (opposite pairs) */
+static const int CV[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+static double weight(int i) {
+    int c2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
+    return c2 == 0 ? 1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+/* Orthogonal mode polynomials e_k(c) (Duenweg-Schiller-Ladd set) */
+static double mode_poly(int k, const int c[3]) {
+    double x = c[0], y = c[1], z = c[2];
+    double c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return x * z;
+    case 10: return (3.0 * c2 - 5.0) * x;
+    case 11: return (3.0 * c2 - 5.0) * y;
+    case 12: return (3.0 * c2 - 5.0) * z;
+    case 13: return (y * y - z * z) * x;
+    case 14: return (z * z - x * x) * y;
+    case 15: return (x * x - y * y) * z;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+    case 18: return (2.0 * c2 - 3.0) * (y * y - z * z);
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------ state */
+struct orc_sim {
+    orc_params p;
+    int64_t N;
+    double E[Q][Q];     /* E[k][i] = e_k(c_i)                */
+    double W[Q];        /* lattice weights                   */
+    double B[Q];        /* b_k = sum_i w_i e_k(c_i)^2         */
+    double *f;          /* [2][Q][N] current populations     */
+    double *fpost;      /* [2][Q][N] post-collision          */
+    double *fnew;       /* [2][Q][N] after streaming         */
+    double *rho;        /* [2][N]                            */
+    double *jm;         /* [2][3][N]                         */
+    double *rt;         /* [2][N] densities seen by SC force */
+    double *F;          /* [2][3][N]                         */
+    unsigned char *solid;     /* particle nodes at X^n       */
+    unsigned char *solid_new; /* particle nodes at X^{n+1}   */
+    orc_particle P;
+    double M_fluid0;
+    double *series;     /* U^{n+1/2}, 3 per step             */
+    int64_t series_len, series_cap;
+};
+
+static int64_t node_index(const orc_sim *s, int x, int y, int z) {
+    return (int64_t)x + (int64_t)s->p.nx * ((int64_t)y + (int64_t)s->p.ny * z);
+}
+
+/* Resolve a lattice position against walls / periodic axes.  Returns 0 when
+ * the position lies in a wall layer (outside the box on a walled axis).   */
+static int resolve(const orc_sim *s, int *x, int *y, int *z) {
+    int n[3] = {s->p.nx, s->p.ny, s->p.nz};
+    int *v[3] = {x, y, z};
+    for (int a = 0; a < 3; a++) {
+        if (*v[a] < 0 || *v[a] >= n[a]) {
+            if (s->p.walls & (1u << a)) return 0;
+            *v[a] = (*v[a] % n[a] + n[a]) % n[a];
+        }
+    }
+    return 1;
+}
+
+/* Mirror of a wall-layer position onto the adjacent box node (clamp). */
+static void mirror(const orc_sim *s, int *x, int *y, int *z) {
+    int n[3] = {s->p.nx, s->p.ny, s->p.nz};
+    int *v[3] = {x, y, z};
+    for (int a = 0; a < 3; a++) {
+        if (*v[a] < 0 || *v[a] >= n[a]) {
+            if (s->p.walls & (1u << a)) *v[a] = *v[a] < 0 ? 0 : n[a] - 1;
+            else *v[a] = (*v[a] % n[a] + n[a]) % n[a];
+        }
+    }
+}
+
+/* minimum-image separation along one axis */
+static double sep(double d, int n, int periodic) {
+    if (periodic) {
+        if (d > 0.5 * n) d -= n;
+        else if (d < -0.5 * n) d += n;
+    }
+    return d;
+}
+
+static void separation(const orc_sim *s, double px, double py, double pz,
+                       const double X[3], double r[3]) {
+    r[0] = sep(px - X[0], s->p.nx, !(s->p.walls & 1u));
+    r[1] = sep(py - X[1], s->p.ny, !(s->p.walls & 2u));
+    r[2] = sep(pz - X[2], s->p.nz, !(s->p.walls & 4u));
+}
+
+/* particle node predicate |x - X|^2 < R^2 (strict), FP64, no contraction */
+static int particle_node(const orc_sim *s, int x, int y, int z, const double X[3]) {
+    if (s->p.radius <= 0.0) return 0;
+    double r[3];
+    separation(s, (double)x, (double)y, (double)z, X, r);
+    double d2 = r[0] * r[0] + r[1] * r[1];
+    d2 = d2 + r[2] * r[2];
+    return d2 < s->p.radius * s->p.radius;
+}
+
+static void cross(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double particle_volume(const orc_sim *s) {
+    return 4.0 / 3.0 * M_PI * s->p.radius * s->p.radius * s->p.radius;
+}
+
+/* ------------------------------------------------------------ Philox4x32-10
+ * Counter-based generator of Salmon, Moraes, Dror, Shaw (SC'11): ten rounds
+ * of two 32x32->64 multiplications with a Weyl key schedule.               */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void philox_key(const orc_sim *s, uint32_t key[2]) {
+    key[0] = (uint32_t)(s->p.seed & 0xffffffffu);
+    key[1] = (uint32_t)(s->p.seed >> 32) ^ (uint32_t)s->p.replica;
+}
+
+static double unit_open(uint32_t w) { return ((double)w + 0.5) * ldexp(1.0, -32); }
+
+/* 36 standard normals for (node, step): 9 Philox blocks, Box-Muller pairs */
+void orc_normals(const orc_sim *s, int64_t node, int64_t step, double z[36]) {
+    uint32_t key[2];
+    philox_key(s, key);
+    for (int b = 0; b < 9; b++) {
+        uint32_t ctr[4] = {(uint32_t)node, (uint32_t)step, (uint32_t)b, 0u}, w[4];
+        orc_philox4x32_10(ctr, key, w);
+        for (int h = 0; h < 2; h++) {
+            double u1 = unit_open(w[2 * h]), u2 = unit_open(w[2 * h + 1]);
+            double r = sqrt(-2.0 * log(u1));
+            double a = 2.0 * M_PI * u2;
+            z[4 * b + 2 * h] = r * cos(a);
+            z[4 * b + 2 * h + 1] = r * sin(a);
+        }
+    }
+}
+
+void orc_basis(double e[19][19], double w[19], double b[19], int32_t c[19][3]) {
+    for (int i = 0; i < Q; i++) {
+        w[i] = weight(i);
+        for (int a = 0; a < 3; a++) c[i][a] = CV[i][a];
+    }
+    for (int k = 0; k < Q; k++) {
+        b[k] = 0.0;
+        for (int i = 0; i < Q; i++) {
+            e[k][i] = mode_poly(k, CV[i]);
+            b[k] += w[i] * e[k][i] * e[k][i];
+        }
+    }
+}
+
+/* ----------------------------------------------------------- construction */
+orc_sim *orc_create(const orc_params *p) {
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->p = *p;
+    s->N = (int64_t)p->nx * p->ny * p->nz;
+    int32_t cdummy[19][3];
+    orc_basis(s->E, s->W, s->B, cdummy);
+    int64_t N = s->N;
+    s->f = (double *)calloc((size_t)(2 * Q * N), sizeof(double));
+    s->fpost = (double *)calloc((size_t)(2 * Q * N), sizeof(double));
+    s->fnew = (double *)calloc((size_t)(2 * Q * N), sizeof(double));
+    s->rho = (double *)calloc((size_t)(2 * N), sizeof(double));
+    s->jm = (double *)calloc((size_t)(6 * N), sizeof(double));
+    s->rt = (double *)calloc((size_t)(2 * N), sizeof(double));
+    s->F = (double *)calloc((size_t)(6 * N), sizeof(double));
+    s->solid = (unsigned char *)calloc((size_t)N, 1);
+    s->solid_new = (unsigned char *)calloc((size_t)N, 1);
+    s->series_cap = 1024;
+    s->series = (double *)calloc((size_t)(3 * s->series_cap), sizeof(double));
+
+    for (int a = 0; a < 3; a++) {
+        s->P.X[a] = p->X0[a];
+        s->P.U[a] = p->U0[a];
+        s->P.W[a] = p->W0[a];
+    }
+    /* initial particle nodes and densities rho_l0 + amp (2u - 1) (Philox tag 1) */
+    uint32_t key[2];
+    philox_key(s, key);
+    s->M_fluid0 = 0.0;
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                s->solid[n] = (unsigned char)particle_node(s, x, y, z, s->P.X);
+                if (s->solid[n]) continue;
+                uint32_t ctr[4] = {(uint32_t)n, 0u, 0u, 1u}, w[4];
+                orc_philox4x32_10(ctr, key, w);
+                for (int l = 0; l < 2; l++) {
+                    double r = p->rho0[l] + p->init_amp * (2.0 * unit_open(w[l]) - 1.0);
+                    for (int i = 0; i < Q; i++) s->f[((int64_t)l * Q + i) * N + n] = s->W[i] * r;
+                    s->M_fluid0 += r;
+                }
+                s->P.n_fluid += 1.0;
+            }
+    return s;
+}
+
+void orc_destroy(orc_sim *s) {
+    if (!s) return;
+    free(s->f); free(s->fpost); free(s->fnew); free(s->rho); free(s->jm);
+    free(s->rt); free(s->F); free(s->solid); free(s->solid_new); free(s->series);
+    free(s);
+}
+
+#define FI(arr, l, i, n) (arr)[((int64_t)(l) * Q + (i)) * N + (n)]
+
+/* ----------------------------------------------------- step 1: moments */
+static void moments(orc_sim *s) {
+    int64_t N = s->N;
+    for (int64_t n = 0; n < N; n++)
+        for (int l = 0; l < 2; l++) {
+            double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            if (!s->solid[n])
+                for (int i = 0; i < Q; i++) {
+                    double fi = FI(s->f, l, i, n);
+                    r += fi;
+                    for (int a = 0; a < 3; a++) j[a] += fi * CV[i][a];
+                }
+            s->rho[l * N + n] = r;
+            for (int a = 0; a < 3; a++) s->jm[(l * 3 + a) * N + n] = j[a];
+        }
+}
+
+/* ------------------------------------------ step 2: virtual wetting layer
+ * Fluid nodes see their own density.  A particle node with at least one
+ * fluid neighbour carries the mean density of its fluid neighbours plus
+ * +Delta rho (component A) / -Delta rho (component B).                   */
+static void virtual_densities(orc_sim *s) {
+    int64_t N = s->N;
+    const orc_params *p = &s->p;
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                if (!s->solid[n]) {
+                    s->rt[n] = s->rho[n];
+                    s->rt[N + n] = s->rho[N + n];
+                    continue;
+                }
+                double sum[2] = {0.0, 0.0};
+                int cnt = 0;
+                for (int i = 1; i < Q; i++) {
+                    int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                    if (!resolve(s, &xn, &yn, &zn)) continue;
+                    int64_t m = node_index(s, xn, yn, zn);
+                    if (s->solid[m]) continue;
+                    sum[0] += s->rho[m];
+                    sum[1] += s->rho[N + m];
+                    cnt++;
+                }
+                if (cnt > 0) {
+                    s->rt[n] = sum[0] / cnt + p->wet_drho;
+                    s->rt[N + n] = sum[1] / cnt - p->wet_drho;
+                } else {
+                    s->rt[n] = 0.0;
+                    s->rt[N + n] = 0.0;
+                }
+            }
+}
+
+/* body-force acceleration of the fluid and external force on the particle */
+static void driving(const orc_sim *s, double af[3], double Fext[3]) {
+    const orc_params *p = &s->p;
+    double V = p->radius > 0.0 ? particle_volume(s) : 0.0;
+    double rho_tot0 = p->rho0[0] + p->rho0[1];
+    for (int a = 0; a < 3; a++) {
+        if (p->force_mode == 1) {
+            af[a] = p->g[a];
+            Fext[a] = V * p->rho_p * p->g[a];
+        } else {
+            Fext[a] = V * (p->rho_p - rho_tot0) * p->g[a];
+            af[a] = s->M_fluid0 > 0.0 ? -Fext[a] / s->M_fluid0 : 0.0;
+        }
+    }
+}
+
+/* --------------------------------------------------- step 3: forces
+ * F_l(x) = -G rho_l(x) sum_i w_i rt_{l'}(x + c_i) c_i + rho_l(x) a_f.
+ * Wall layers mirror the adjacent fluid node (neutral walls).  The share
+ * of the force coming from particle nodes is returned for the reaction
+ * on the particle (force Fv, torque Tv about X^n).                       */
+static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3]) {
+    int64_t N = s->N;
+    const orc_params *p = &s->p;
+    double af[3], Fext[3];
+    driving(s, af, Fext);
+    for (int a = 0; a < 3; a++) { Fv[a] = 0.0; Tv[a] = 0.0; }
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                for (int l = 0; l < 2; l++)
+                    for (int a = 0; a < 3; a++) F[(l * 3 + a) * N + n] = 0.0;
+                if (s->solid[n]) continue;
+                double sumo[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                for (int i = 1; i < Q; i++) {
+                    int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                    int inside = resolve(s, &xn, &yn, &zn);
+                    if (!inside) {
+                        xn = x + CV[i][0]; yn = y + CV[i][1]; zn = z + CV[i][2];
+                        mirror(s, &xn, &yn, &zn);
+                    }
+                    int64_t m = node_index(s, xn, yn, zn);
+                    double link[2][3];
+                    for (int l = 0; l < 2; l++) {
+                        double other = s->rt[(1 - l) * N + m];
+                        for (int a = 0; a < 3; a++) {
+                            link[l][a] = -p->G * s->rho[l * N + n] * s->W[i] * other * CV[i][a];
+                            sumo[l][a] += link[l][a];
+                        }
+                    }
+                    if (inside && s->solid[m]) {
+                        double fl[3], r[3], t[3];
+                        for (int a = 0; a < 3; a++) fl[a] = link[0][a] + link[1][a];
+                        separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
+                                   s->P.X, r);
+                        cross(r, fl, t);
+                        for (int a = 0; a < 3; a++) { Fv[a] += fl[a]; Tv[a] += t[a]; }
+                    }
+                }
+                for (int l = 0; l < 2; l++)
+                    for (int a = 0; a < 3; a++)
+                        F[(l * 3 + a) * N + n] = sumo[l][a] + s->rho[l * N + n] * af[a];
+            }
+}
+
+void orc_forces(const orc_sim *s, double *F) {
+    orc_sim *m = (orc_sim *)s; /* moments / virtual densities are scratch */
+    moments(m);
+    virtual_densities(m);
+    double Fv[3], Tv[3];
+    forces_impl(s, F, Fv, Tv);
+}
+
+/* ---------------------------------------------- steps 4-6: collision
+ * Both components share the hydrodynamic velocity
+ *   u = (j_A + j_B + (F_A + F_B)/2) / rho.
+ * Per component the modes m_k = sum_i e_k(c_i) f_i relax separately;
+ * stress modes get Guo forcing in mode space; non-conserved modes get
+ * noise sqrt(mu rho_l b_k (1 - gamma_k^2)) r with mu = kT / c_s^2.       */
+void orc_collide_node(const orc_sim *s, const double fin[2][19], const double F[2][3],
+                      const double noise[36], double fout[2][19]) {
+    const orc_params *p = &s->p;
+    double gs = 1.0 - 1.0 / p->tau_shear, gb = 1.0 - 1.0 / p->tau_bulk;
+    double gj = 1.0 - 1.0 / p->tau_mom, gg = 1.0 - 1.0 / p->tau_ghost;
+    double mu = 3.0 * p->kT;
+    double m[2][Q], rl[2], jl[2][3];
+    for (int l = 0; l < 2; l++) {
+        for (int k = 0; k < Q; k++) {
+            m[l][k] = 0.0;
+            for (int i = 0; i < Q; i++) m[l][k] += s->E[k][i] * fin[l][i];
+        }
+        rl[l] = m[l][0];
+        for (int a = 0; a < 3; a++) jl[l][a] = m[l][1 + a];
+    }
+    double rho = rl[0] + rl[1];
+    double u[3];
+    for (int a = 0; a < 3; a++) u[a] = (jl[0][a] + jl[1][a] + 0.5 * (F[0][a] + F[1][a])) / rho;
+    double ra = rl[0] > 0.0 ? rl[0] : 0.0, rb = rl[1] > 0.0 ? rl[1] : 0.0;
+    double xid[3] = {0.0, 0.0, 0.0};
+    if (mu > 0.0 && p->noise_diffusive && rho > 0.0) {
+        double amp = sqrt(mu * s->B[1] * (1.0 - gj * gj) * ra * rb / rho);
+        for (int a = 0; a < 3; a++) xid[a] = amp * noise[30 + a];
+    }
+    for (int l = 0; l < 2; l++) {
+        double ms[Q];
+        double r = rl[l], rp = r > 0.0 ? r : 0.0;
+        const double *Fl = F[l];
+        double sigma = l == 0 ? 1.0 : -1.0;
+        ms[0] = r;
+        for (int a = 0; a < 3; a++)
+            ms[1 + a] = r * u[a] + gj * (jl[l][a] + 0.5 * Fl[a] - r * u[a]) + 0.5 * Fl[a] +
+                        sigma * xid[a];
+        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        double uF = u[0] * Fl[0] + u[1] * Fl[1] + u[2] * Fl[2];
+        double meq[10], phi[10], gam[10];
+        meq[4] = r * uu;
+        meq[5] = r * (3.0 * u[0] * u[0] - uu);
+        meq[6] = r * (u[1] * u[1] - u[2] * u[2]);
+        meq[7] = r * u[0] * u[1];
+        meq[8] = r * u[1] * u[2];
+        meq[9] = r * u[0] * u[2];
+        phi[4] = 2.0 * uF;
+        phi[5] = 2.0 * (3.0 * u[0] * Fl[0] - uF);
+        phi[6] = 2.0 * (u[1] * Fl[1] - u[2] * Fl[2]);
+        phi[7] = u[0] * Fl[1] + u[1] * Fl[0];
+        phi[8] = u[1] * Fl[2] + u[2] * Fl[1];
+        phi[9] = u[0] * Fl[2] + u[2] * Fl[0];
+        gam[4] = gb;
+        for (int k = 5; k <= 9; k++) gam[k] = gs;
+        for (int k = 4; k <= 9; k++) {
+            ms[k] = meq[k] + gam[k] * (m[l][k] - meq[k]) + 0.5 * (1.0 + gam[k]) * phi[k];
+            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gam[k] * gam[k])) * noise[15 * l + k - 4];
+        }
+        for (int k = 10; k < Q; k++) {
+            ms[k] = gg * m[l][k];
+            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gg * gg)) * noise[15 * l + k - 4];
+        }
+        for (int i = 0; i < Q; i++) {
+            double acc = 0.0;
+            for (int k = 0; k < Q; k++) acc += s->E[k][i] * ms[k] / s->B[k];
+            fout[l][i] = s->W[i] * acc;
+        }
+    }
+}
+
+static void collide(orc_sim *s) {
+    int64_t N = s->N;
+    double zero[36];
+    memset(zero, 0, sizeof(zero));
+    for (int64_t n = 0; n < N; n++) {
+        if (s->solid[n]) {
+            for (int l = 0; l < 2; l++)
+                for (int i = 0; i < Q; i++) FI(s->fpost, l, i, n) = 0.0;
+            continue;
+        }
+        double fin[2][Q], fout[2][Q], F[2][3], z[36];
+        for (int l = 0; l < 2; l++) {
+            for (int i = 0; i < Q; i++) fin[l][i] = FI(s->f, l, i, n);
+            for (int a = 0; a < 3; a++) F[l][a] = s->F[(l * 3 + a) * N + n];
+        }
+        if (s->p.kT > 0.0) orc_normals(s, n, s->P.step, z);
+        else memcpy(z, zero, sizeof(z));
+        orc_collide_node(s, fin, F, z, fout);
+        for (int l = 0; l < 2; l++)
+            for (int i = 0; i < Q; i++) FI(s->fpost, l, i, n) = fout[l][i];
+    }
+}
+
+static void series_push(orc_sim *s) {
+    if (s->series_len == s->series_cap) {
+        s->series_cap *= 2;
+        s->series = (double *)realloc(s->series, (size_t)(3 * s->series_cap) * sizeof(double));
+    }
+    for (int a = 0; a < 3; a++) s->series[3 * s->series_len + a] = s->P.U[a];
+    s->series_len++;
+}
+
+/* ------------------------------------------------------------ one step */
+static void one_step(orc_sim *s) {
+    int64_t N = s->N;
+    const orc_params *p = &s->p;
+    orc_particle *P = &s->P;
+
+    moments(s);                 /* 1 */
+    virtual_densities(s);       /* 2 */
+    double Fv[3], Tv[3];
+    forces_impl(s, s->F, Fv, Tv); /* 3 */
+    collide(s);                 /* 4-6 */
+
+    /* 7: streaming with half-way bounce-back on walls and moving-wall
+     * bounce-back on particle nodes (momentum exchange on each link)     */
+    memset(s->fnew, 0, (size_t)(2 * Q * N) * sizeof(double));
+    double dp[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dMbb[2] = {0, 0};
+    int64_t links = 0;
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                if (s->solid[n]) continue;
+                for (int l = 0; l < 2; l++) FI(s->fnew, l, 0, n) = FI(s->fpost, l, 0, n);
+                for (int i = 1; i < Q; i++) {
+                    int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                    int io = opposite(i);
+                    if (!resolve(s, &xn, &yn, &zn)) {
+                        for (int l = 0; l < 2; l++) FI(s->fnew, l, io, n) = FI(s->fpost, l, i, n);
+                        continue;
+                    }
+                    int64_t m = node_index(s, xn, yn, zn);
+                    if (s->solid[m]) {
+                        double r[3], w[3], ub[3];
+                        separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
+                                   P->X, r);
+                        cross(P->W, r, w);
+                        for (int a = 0; a < 3; a++) ub[a] = P->U[a] + w[a];
+                        double cu = CV[i][0] * ub[0] + CV[i][1] * ub[1] + CV[i][2] * ub[2];
+                        double lp[3] = {0, 0, 0};
+                        for (int l = 0; l < 2; l++) {
+                            double corr = 6.0 * s->W[i] * s->rho[l * N + n] * cu;
+                            double fs = FI(s->fpost, l, i, n);
+                            FI(s->fnew, l, io, n) = fs - corr;
+                            for (int a = 0; a < 3; a++) lp[a] += (2.0 * fs - corr) * CV[i][a];
+                            dMbb[l] -= corr;
+                        }
+                        double t[3];
+                        cross(r, lp, t);
+                        for (int a = 0; a < 3; a++) { dp[a] += lp[a]; dl[a] += t[a]; }
+                        links++;
+                        continue;
+                    }
+                    for (int l = 0; l < 2; l++) FI(s->fnew, l, i, m) = FI(s->fpost, l, i, n);
+                }
+            }
+
+    /* 8: leap-frog Newton-Euler update of the sphere */
+    double af[3], Fext[3];
+    driving(s, af, Fext);
+    if (p->radius > 0.0) {
+        double mp = p->rho_p * particle_volume(s);
+        double Ip = 0.4 * mp * p->radius * p->radius;
+        for (int a = 0; a < 3; a++) {
+            P->F[a] = dp[a] - Fv[a] + Fext[a] + P->Pev[a];
+            P->T[a] = dl[a] - Tv[a] + P->Lev[a];
+            if (!p->fixed_velocity) {
+                P->U[a] += P->F[a] / mp;
+                P->W[a] += P->T[a] / Ip;
+            }
+        }
+        int n3[3] = {p->nx, p->ny, p->nz};
+        for (int a = 0; a < 3; a++) {
+            P->X[a] += P->U[a];
+            if (!(p->walls & (1u << a))) {
+                if (P->X[a] >= n3[a]) P->X[a] -= n3[a];
+                else if (P->X[a] < 0.0) P->X[a] += n3[a];
+            }
+            P->Pev[a] = 0.0;
+            P->Lev[a] = 0.0;
+        }
+    }
+    P->n_links = links;
+    series_push(s);
+
+    /* 9: cover / uncover against the particle nodes at X^{n+1} */
+    double dMcov[2] = {0, 0}, dMunc[2] = {0, 0};
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                s->solid_new[n] = (unsigned char)particle_node(s, x, y, z, P->X);
+            }
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                if (!s->solid[n] && s->solid_new[n]) { /* covered */
+                    double j[3] = {0, 0, 0}, r[3], t[3];
+                    for (int l = 0; l < 2; l++) {
+                        double rl = 0.0;
+                        for (int i = 0; i < Q; i++) {
+                            double fi = FI(s->fnew, l, i, n);
+                            rl += fi;
+                            for (int a = 0; a < 3; a++) j[a] += fi * CV[i][a];
+                        }
+                        dMcov[l] -= rl;
+                    }
+                    separation(s, x, y, z, P->X, r);
+                    cross(r, j, t);
+                    for (int a = 0; a < 3; a++) { P->Pev[a] += j[a]; P->Lev[a] += t[a]; }
+                    P->n_covered++;
+                }
+            }
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                int64_t n = node_index(s, x, y, z);
+                if (!(s->solid[n] && !s->solid_new[n])) continue; /* uncovered only */
+                double rb[2] = {0, 0};
+                int cnt = 0;
+                for (int i = 1; i < Q; i++) {
+                    int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                    if (!resolve(s, &xn, &yn, &zn)) continue;
+                    int64_t m = node_index(s, xn, yn, zn);
+                    if (s->solid[m] || s->solid_new[m]) continue;
+                    for (int l = 0; l < 2; l++)
+                        for (int k = 0; k < Q; k++) rb[l] += FI(s->fnew, l, k, m);
+                    cnt++;
+                }
+                for (int l = 0; l < 2; l++) rb[l] = cnt > 0 ? rb[l] / cnt : p->rho0[l];
+                double r[3], w[3], u[3];
+                separation(s, x, y, z, P->X, r);
+                cross(P->W, r, w);
+                for (int a = 0; a < 3; a++) u[a] = P->U[a] + w[a];
+                double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                for (int l = 0; l < 2; l++) {
+                    for (int i = 0; i < Q; i++) {
+                        double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+                        FI(s->fnew, l, i, n) = s->W[i] * rb[l] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                    }
+                    dMunc[l] += rb[l];
+                }
+                double mom[3], t[3];
+                for (int a = 0; a < 3; a++) mom[a] = (rb[0] + rb[1]) * u[a];
+                cross(r, mom, t);
+                for (int a = 0; a < 3; a++) { P->Pev[a] -= mom[a]; P->Lev[a] -= t[a]; }
+                P->n_uncovered++;
+            }
+    /* covered nodes drop their populations */
+    for (int64_t n = 0; n < N; n++)
+        if (s->solid_new[n])
+            for (int l = 0; l < 2; l++)
+                for (int i = 0; i < Q; i++) FI(s->fnew, l, i, n) = 0.0;
+
+    /* 10: global mass correction over Phi^{n+1} */
+    double nf = 0.0;
+    for (int64_t n = 0; n < N; n++) nf += s->solid_new[n] ? 0.0 : 1.0;
+    for (int l = 0; l < 2; l++) P->delta[l] = -(dMbb[l] + dMcov[l] + dMunc[l]) / nf;
+    for (int64_t n = 0; n < N; n++) {
+        if (s->solid_new[n]) continue;
+        for (int l = 0; l < 2; l++)
+            for (int i = 0; i < Q; i++) FI(s->fnew, l, i, n) += s->W[i] * P->delta[l];
+    }
+    P->n_fluid = nf;
+
+    double *t = s->f; s->f = s->fnew; s->fnew = t;
+    unsigned char *u8 = s->solid; s->solid = s->solid_new; s->solid_new = u8;
+    P->step++;
+}
+
+void orc_step(orc_sim *s, int32_t nsteps) {
+    for (int32_t k = 0; k < nsteps; k++) one_step(s);
+}
+
+void orc_get_populations(const orc_sim *s, double *f) {
+    memcpy(f, s->f, (size_t)(2 * Q * s->N) * sizeof(double));
+}
+
+void orc_set_populations(orc_sim *s, const double *f) {
+    memcpy(s->f, f, (size_t)(2 * Q * s->N) * sizeof(double));
+}
+
+void orc_get_particle(const orc_sim *s, orc_particle *out) { *out = s->P; }
+
+void orc_set_particle(orc_sim *s, const orc_particle *in) {
+    s->P = *in;
+    const orc_params *p = &s->p;
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++)
+                s->solid[node_index(s, x, y, z)] = (unsigned char)particle_node(s, x, y, z, s->P.X);
+}
+
+void orc_get_fields(const orc_sim *s, double *rho, double *u) {
+    orc_sim *m = (orc_sim *)s;
+    int64_t N = s->N;
+    double *F = (double *)malloc((size_t)(6 * N) * sizeof(double));
+    orc_forces(s, F);
+    for (int64_t n = 0; n < N; n++) {
+        double rt = s->rho[n] + s->rho[N + n];
+        rho[n] = s->rho[n];
+        rho[N + n] = s->rho[N + n];
+        for (int a = 0; a < 3; a++) {
+            if (m->solid[n] || rt == 0.0) { u[a * N + n] = 0.0; continue; }
+            u[a * N + n] = (s->jm[a * N + n] + s->jm[(3 + a) * N + n] +
+                            0.5 * (F[a * N + n] + F[(3 + a) * N + n])) / rt;
+        }
+    }
+    free(F);
+}
+
+void orc_observables(const orc_sim *s, double mass[2], double mom[3]) {
+    int64_t N = s->N;
+    mass[0] = mass[1] = 0.0;
+    mom[0] = mom[1] = mom[2] = 0.0;
+    for (int64_t n = 0; n < N; n++) {
+        if (s->solid[n]) continue;
+        for (int l = 0; l < 2; l++)
+            for (int i = 0; i < Q; i++) {
+                double fi = FI(s->f, l, i, n);
+                mass[l] += fi;
+                for (int a = 0; a < 3; a++) mom[a] += fi * CV[i][a];
+            }
+    }
+}
+
+int64_t orc_u_series(const orc_sim *s, double *u3, int64_t cap) {
+    int64_t n = s->series_len < cap ? s->series_len : cap;
+    memcpy(u3, s->series, (size_t)(3 * n) * sizeof(double));
+    return s->series_len;
+}

@@ -1,0 +1,22 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long CPU run (oracle physics at larger sizes)")
+
+
+@pytest.fixture(scope="session")
+def oracle_lib():
+    from oracle import build as ob
+    from oracle import oracle as om
+    if not os.path.exists(om.LIB_PATH):
+        ob.build()
+    return om
