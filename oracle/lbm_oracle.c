@@ -195,7 +195,9 @@ static void philox_key(const orc_sim *s, uint32_t key[2]) {
 
 static double unit_open(uint32_t w) { return ((double)w + 0.5) * ldexp(1.0, -32); }
 
-/* 36 standard normals for (node, step): 9 Philox blocks, Box-Muller pairs */
+/* 36 standard normals for (node, step): 9 Philox blocks, Box-Muller pairs.
+ * Block b gives normals 4b..4b+3.  Normals 16 l + (k - 4) drive mode k of
+ * component l (k = 4..18); normals 32..34 the species-momentum noise.      */
 void orc_normals(const orc_sim *s, int64_t node, int64_t step, double z[36]) {
     uint32_t key[2];
     philox_key(s, key);
@@ -438,7 +440,7 @@ void orc_collide_node(const orc_sim *s, const double fin[2][19], const double F[
     double xid[3] = {0.0, 0.0, 0.0};
     if (mu > 0.0 && p->noise_diffusive && rho > 0.0) {
         double amp = sqrt(mu * s->B[1] * (1.0 - gj * gj) * ra * rb / rho);
-        for (int a = 0; a < 3; a++) xid[a] = amp * noise[30 + a];
+        for (int a = 0; a < 3; a++) xid[a] = amp * noise[32 + a];
     }
     for (int l = 0; l < 2; l++) {
         double ms[Q];
@@ -468,11 +470,11 @@ void orc_collide_node(const orc_sim *s, const double fin[2][19], const double F[
         for (int k = 5; k <= 9; k++) gam[k] = gs;
         for (int k = 4; k <= 9; k++) {
             ms[k] = meq[k] + gam[k] * (m[l][k] - meq[k]) + 0.5 * (1.0 + gam[k]) * phi[k];
-            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gam[k] * gam[k])) * noise[15 * l + k - 4];
+            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gam[k] * gam[k])) * noise[16 * l + k - 4];
         }
         for (int k = 10; k < Q; k++) {
             ms[k] = gg * m[l][k];
-            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gg * gg)) * noise[15 * l + k - 4];
+            if (mu > 0.0) ms[k] += sqrt(mu * rp * s->B[k] * (1.0 - gg * gg)) * noise[16 * l + k - 4];
         }
         for (int i = 0; i < Q; i++) {
             double acc = 0.0;
