@@ -1,0 +1,179 @@
+/*
+ * lbm.h — C ABI of the MI355X (gfx950) library for the fluctuating
+ * two-component D3Q19 lattice Boltzmann step with a settling, wettable,
+ * finite-size sphere (Xue, Biferale, Sbragaglia, Toschi, "A lattice
+ * Boltzmann study of particle settling in a fluctuating multicomponent fluid
+ * under confinement").
+ *
+ * What one step computes (Sec. 2 of the paper, "Methodology"):
+ *   - moments rho_l, rho_tot v of the populations f_{l i} (eq. density);
+ *   - the Shan-Chen force between components (eq. sc-force) plus the body
+ *     force, with a virtual wetting layer on particle nodes (mean density of
+ *     the fluid neighbours + / - Delta rho) and neutral (mirror) walls;
+ *   - MRT collision in an orthogonal mode basis with Guo forcing at the
+ *     hydrodynamic velocity v + (F_A + F_B)/(2 rho_tot), and thermal noise on
+ *     every non-conserved mode obeying fluctuation-dissipation (eq. lbe);
+ *   - streaming with half-way bounce-back on the walls and moving-wall
+ *     bounce-back on the sphere, with momentum exchange on every link;
+ *   - leap-frog Newton-Euler update of the sphere under the external force
+ *     of Sec. 3, eq. (fp), cover/uncover of nodes, global mass correction.
+ *
+ * Conventions.  Lattice units.  Node (x, y, z), 0 <= x < nx etc., sits at
+ * position (x, y, z); a walled axis has its walls half-way outside the first
+ * and last node.  Populations exchanged with the host are FP64 arrays laid
+ * out [component 2][direction 19][z][y][x].  Direction order: rest;
+ * +x, -x, +y, -y, +z, -z; (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0);
+ * (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1); (0,1,1), (0,-1,-1), (0,1,-1),
+ * (0,-1,1).
+ *
+ * Memory ownership.  The caller allocates one device workspace of
+ * lbm_workspace_bytes() bytes (256-byte aligned) and keeps it alive until
+ * lbm_destroy(); the library never allocates or frees device memory.  The
+ * library copies the parameters and owns the host context.  Every host array
+ * is caller-owned.
+ *
+ * Errors.  Every call returns an lbm_status; nothing is thrown or aborted
+ * across the ABI.  Invalid arguments return LBM_EINVAL before any device
+ * work.  lbm_last_error() gives a message.  A step that produces a
+ * non-finite or negative density, or a sphere that leaves its channel, sets
+ * a sticky flag: the state queries then return LBM_EUNSTABLE (after filling
+ * their outputs) until lbm_restore().
+ *
+ * Streams.  All device work is enqueued on the hip_stream given to
+ * lbm_init (NULL = the default stream).  lbm_step is asynchronous; the query
+ * calls synchronise that stream.  A context is not thread-safe.
+ */
+#ifndef LBM_H
+#define LBM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument or configuration            */
+    LBM_ENOMEM = -2,    /* workspace too small or misaligned            */
+    LBM_EDEVICE = -3,   /* HIP runtime error                            */
+    LBM_EUNSTABLE = -4, /* the run went unstable (sticky)               */
+    LBM_ESTATE = -5     /* call not valid in the current context state  */
+};
+
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };
+
+/* One replica of the problem (Sec. 3 set-up: square channel, sphere at the
+ * centre of the cross-section, body force along z). */
+typedef struct lbm_params {
+    int32_t nx, ny, nz;        /* nodes per axis, 2 <= n, nx <= 256                       */
+    uint32_t walls;            /* bit0 x, bit1 y, bit2 z walls; other axes periodic       */
+    double rho0[2];            /* reference densities of A (majority) and B               */
+    double init_amp;           /* initial densities rho0_l + init_amp (2u - 1), u uniform */
+    double G;                  /* Shan-Chen coupling (eq. sc-force)                       */
+    double tau_shear, tau_bulk, tau_mom, tau_ghost; /* relaxation times, > 1/2            */
+    double kT;                 /* thermal energy (>= 0)                                   */
+    uint64_t seed;             /* Philox key = (lo32(seed), hi32(seed) ^ replica)         */
+    int32_t replica;           /* replica index entering the key                          */
+    double g[3];               /* body-force acceleration g (Sec. 3)                      */
+    int32_t force_mode;        /* 0: sphere gets F_p = V (rho_p - rho_tot0) g (eq. fp),
+                                     fluid gets -F_p / M_fluid (net zero); 1: fluid rho g,
+                                     sphere rho_p V g                                       */
+    double radius;             /* sphere radius d/2 (<= 0: no sphere)                     */
+    double rho_p;              /* sphere density                                          */
+    double wet_drho;           /* wetting-layer offset Delta rho (+A, -B)                 */
+    double X0[3], U0[3], W0[3];/* initial centre, velocity, angular velocity              */
+    int32_t noise_diffusive;   /* 1: noise on the species-momentum (diffusion) mode       */
+    int32_t fixed_velocity;    /* 1: sphere moves with U0, W0 (prescribed)                */
+    int32_t series_cap;        /* length of the per-step U ring buffer (>= 1)             */
+    int32_t reserved;
+} lbm_params;
+
+/* Sphere state after the last completed step n. */
+typedef struct lbm_particle {
+    double X[3], U[3], W[3];   /* X^n, U^{n-1/2}, Omega^{n-1/2}                           */
+    double F[3], T[3];         /* total force / torque of step n-1                        */
+    double Pev[3], Lev[3];     /* cover/uncover momentum pending for the next step        */
+    double delta[2];           /* mass correction per component                           */
+    double n_fluid;            /* fluid nodes |Phi^n|                                      */
+    int64_t step;              /* n                                                       */
+    int64_t n_covered, n_uncovered, n_links;
+} lbm_particle;
+
+/* Global observables of the current state of one replica. */
+typedef struct lbm_obs {
+    double mass[2];            /* sum of rho_l over fluid nodes                            */
+    double momentum[3];        /* sum of (j_A + j_B) over fluid nodes                      */
+    double u2_mean;            /* mean |v_H|^2 over fluid nodes                            */
+    double uz_mean;            /* mean v_H,z over fluid nodes                              */
+    double n_fluid;
+    double *uz_profile;        /* optional [ny][nx]: mean v_H,z over fluid nodes of each
+                                  (x, y) column; caller-owned, may be NULL                  */
+} lbm_obs;
+
+/* Workspace size for n_replicas parameter sets p[0..n_replicas-1] stored in
+ * the given precision (LBM_FP64 / LBM_FP32 / LBM_FP16). */
+int lbm_workspace_bytes(const lbm_params *p, int32_t n_replicas, int32_t precision,
+                        size_t *bytes);
+
+/* Validate, lay out the workspace, write the initial state (densities
+ * rho0_l + init_amp (2u - 1) from Philox counter (node, 0, 0, 1), fluid at
+ * rest) and return a context.  dev_ws: device pointer, 256-byte aligned. */
+int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision, void *dev_ws,
+             size_t ws_bytes, void *hip_stream, lbm_ctx **out);
+
+/* Advance every replica by nsteps (asynchronous). */
+int lbm_step(lbm_ctx *c, int32_t nsteps);
+
+/* Blocks until the context's stream has drained. */
+int lbm_sync(lbm_ctx *c);
+
+int lbm_particle_state(lbm_ctx *c, int32_t replica, lbm_particle *out);
+int lbm_observables(lbm_ctx *c, int32_t replica, lbm_obs *o);
+
+/* f_{l i}(x, n) (after streaming and mass correction, particle nodes 0) of one
+ * replica into host_f[2][19][nz][ny][nx]. */
+int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f);
+
+/* rho_l and the hydrodynamic velocity v_H per node (particle nodes 0):
+ * host_rho[2][nz][ny][nx], host_u[3][nz][ny][nx]. */
+int lbm_fields(lbm_ctx *c, int32_t replica, double *host_rho, double *host_u);
+
+/* U^{n+1/2} of the last min(steps, series_cap) steps, oldest first, into
+ * host_u3[k][3]; *count = number written. */
+int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t cap, int64_t *count);
+
+/* Checkpoint: the complete state needed to resume bit-for-bit. */
+int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes);
+int lbm_checkpoint(lbm_ctx *c, void *dev_dst);
+int lbm_restore(lbm_ctx *c, const void *dev_src);
+
+/* Launch shape of the main kernel: block threads (256) and z-chunk length.
+ * Rebuilds the tiling; the physics is unchanged. */
+int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk);
+int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk);
+
+/* 0: plain launches; k > 0: lbm_step replays a HIP graph of k steps (k even;
+ * needs a non-default stream); leftover steps run as plain launches. */
+int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph);
+
+/* Timing of the main kernel: while enabled, every plain-launch step records
+ * HIP events around the main kernel on the context stream.
+ * lbm_timing_read returns the mean duration (ms) and the number of timed
+ * launches since it was enabled. */
+int lbm_timing(lbm_ctx *c, int32_t enable);
+int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count);
+
+/* Algorithmic bytes one step of the main kernel moves (read + write of
+ * 2 x 19 populations per node, all replicas). */
+int lbm_step_bytes(lbm_ctx *c, double *bytes);
+
+void lbm_destroy(lbm_ctx *c);
+const char *lbm_last_error(const lbm_ctx *c);  /* NULL ctx: last lbm_init error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,723 @@
+// Host implementation of the C ABI declared in include/lbm.h: validation,
+// workspace layout, initial state, step scheduling (plain launches or HIP
+// graph replays), state queries and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.h"
+#include "lbm_types.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t ALIGN = 256;
+constexpr int MAIN_BLOCK_MIN = 256;
+constexpr int K3_BLOCK = 256;
+constexpr int INIT_BLOCK = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : prec == LBM_FP32 ? 4 : 2; }
+
+bool has_sphere(const lbm_params &p) { return p.radius > 0.0; }
+
+int bbox_edge(const lbm_params &p) {
+    return has_sphere(p) ? 2 * (int)std::ceil(p.radius) + 7 : 0;
+}
+
+struct Layout {
+    size_t tables, desc, state, pop[2], part1, part3, raw, vrho, flags, series, aux, total;
+    std::vector<int64_t> pop_off, bbox_off, part1_off, part3_off, series_off, init_wg;
+    std::vector<int> S, k3_count;
+    int64_t Ntot = 0, S3tot = 0, part1_tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
+    size_t aux_doubles = 0;
+};
+
+// largest main-kernel tile count a replica can need (one row, one plane)
+int64_t max_tiles(const lbm_params &p) {
+    const int ty = std::max(1, std::min(p.ny, MAIN_BLOCK_MIN / p.nx));
+    return (int64_t)((p.ny + ty - 1) / ty) * p.nz;
+}
+
+Layout plan(const lbm_params *p, int n, int prec) {
+    Layout L;
+    const size_t es = elem_size(prec);
+    L.pop_off.resize(n); L.bbox_off.resize(n); L.part1_off.resize(n); L.part3_off.resize(n);
+    L.series_off.resize(n); L.S.resize(n); L.k3_count.resize(n); L.init_wg.resize(n);
+    size_t max_cols = 0;
+    for (int r = 0; r < n; r++) {
+        const int64_t N = (int64_t)p[r].nx * p[r].ny * p[r].nz;
+        L.pop_off[r] = 38 * L.Ntot;
+        L.Ntot += N;
+        L.S[r] = bbox_edge(p[r]);
+        const int64_t S3 = (int64_t)L.S[r] * L.S[r] * L.S[r];
+        L.bbox_off[r] = L.S3tot;
+        L.S3tot += S3;
+        L.part1_off[r] = L.part1_tot;
+        L.part1_tot += has_sphere(p[r]) ? max_tiles(p[r]) * PART : 0;
+        L.k3_count[r] = has_sphere(p[r]) ? (int)((S3 + K3_BLOCK - 1) / K3_BLOCK) : 1;
+        L.part3_off[r] = L.part3_tot;
+        L.part3_tot += (int64_t)L.k3_count[r] * PART;
+        L.series_off[r] = L.series_tot;
+        L.series_tot += 3 * (int64_t)p[r].series_cap;
+        L.init_wg[r] = (N + INIT_BLOCK - 1) / INIT_BLOCK;
+        L.init_tot += L.init_wg[r];
+        max_cols = std::max(max_cols, (size_t)8 * p[r].nx * p[r].ny);
+    }
+    L.aux_doubles = std::max(max_cols, (size_t)(2 * L.init_tot));
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    L.tables = take(sizeof(int32_t) * 3 * (n + 1));
+    L.desc = take(sizeof(RepDesc) * n);
+    L.state = take(sizeof(RepState) * n);
+    L.pop[0] = take(38 * L.Ntot * es);
+    L.pop[1] = take(38 * L.Ntot * es);
+    L.part1 = take(sizeof(double) * std::max<int64_t>(L.part1_tot, 1));
+    L.part3 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
+    L.raw = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
+    L.vrho = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
+    L.flags = take(std::max<int64_t>(L.S3tot, 1));
+    L.series = take(sizeof(double) * std::max<int64_t>(L.series_tot, 1));
+    L.aux = take(sizeof(double) * L.aux_doubles);
+    L.total = o;
+    return L;
+}
+
+std::string fmt(const char *f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof(buf), f, ap);
+    va_end(ap);
+    return buf;
+}
+
+std::string validate(const lbm_params *p, int n, int prec) {
+    if (!p) return "params is NULL";
+    if (n < 1) return "n_replicas must be >= 1";
+    if (prec < LBM_FP64 || prec > LBM_FP16) return "precision must be LBM_FP64, LBM_FP32 or LBM_FP16";
+    for (int r = 0; r < n; r++) {
+        const lbm_params &q = p[r];
+        const int nn[3] = {q.nx, q.ny, q.nz};
+        if (q.nx < 2 || q.ny < 2 || q.nz < 2) return fmt("replica %d: every axis needs >= 2 nodes", r);
+        if (q.nx > MAIN_BLOCK_MIN) return fmt("replica %d: nx = %d exceeds %d", r, q.nx, MAIN_BLOCK_MIN);
+        if ((int64_t)q.nx * q.ny * q.nz >= (int64_t(1) << 31) / 38)
+            return fmt("replica %d: lattice too large for one replica", r);
+        if (q.walls > 7u) return fmt("replica %d: walls must be a 3-bit mask", r);
+        if (!(q.rho0[0] > 0.0) || !(q.rho0[1] > 0.0)) return fmt("replica %d: rho0 must be > 0", r);
+        if (!(q.init_amp >= 0.0) || q.init_amp >= std::min(q.rho0[0], q.rho0[1]))
+            return fmt("replica %d: init_amp must be in [0, min(rho0))", r);
+        const double taus[4] = {q.tau_shear, q.tau_bulk, q.tau_mom, q.tau_ghost};
+        for (double t : taus)
+            if (!(t > 0.5) || !std::isfinite(t)) return fmt("replica %d: relaxation times must be > 1/2", r);
+        if (!(q.kT >= 0.0) || !std::isfinite(q.kT)) return fmt("replica %d: kT must be >= 0", r);
+        if (!std::isfinite(q.G)) return fmt("replica %d: G must be finite", r);
+        if (q.force_mode != 0 && q.force_mode != 1) return fmt("replica %d: force_mode must be 0 or 1", r);
+        if (q.series_cap < 1) return fmt("replica %d: series_cap must be >= 1", r);
+        for (int a = 0; a < 3; a++)
+            if (!std::isfinite(q.g[a]) || !std::isfinite(q.U0[a]) || !std::isfinite(q.W0[a]) ||
+                !std::isfinite(q.X0[a]))
+                return fmt("replica %d: non-finite vector parameter", r);
+        if (has_sphere(q)) {
+            if (!(q.rho_p > 0.0)) return fmt("replica %d: rho_p must be > 0", r);
+            const int S = bbox_edge(q);
+            for (int a = 0; a < 3; a++) {
+                const bool wall = q.walls & (1u << a);
+                if (wall) {
+                    if (q.X0[a] - q.radius < 1.0 || q.X0[a] + q.radius > nn[a] - 2.0)
+                        return fmt("replica %d: sphere needs one node of clearance from the walls on axis %d", r, a);
+                } else {
+                    if (S > nn[a]) return fmt("replica %d: periodic axis %d shorter than 2 ceil(R) + 7", r, a);
+                    if (q.X0[a] < 0.0 || q.X0[a] >= nn[a]) return fmt("replica %d: X0 outside the box", r);
+                }
+                if (!(std::fabs(q.U0[a]) < 0.5)) return fmt("replica %d: |U0| must be < 0.5", r);
+            }
+        }
+    }
+    return "";
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<lbm_params> p;
+    int nrep = 0, prec = 0;
+    size_t es = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    Layout L;
+    std::vector<RepDesc> desc;
+    std::vector<int32_t> tables;
+    int block = 256, cz = 8;
+    int main_grid = 0, k3_grid = 0, init_grid = 0;
+    size_t lds = 0;
+    int cur = 0;
+    int tau1 = 0;
+    int graph_steps = 0, graph_parity = -1;
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::string err;
+
+    RepDesc *d_desc() { return reinterpret_cast<RepDesc *>(ws + L.desc); }
+    RepState *d_state() { return reinterpret_cast<RepState *>(ws + L.state); }
+    int32_t *d_tables() { return reinterpret_cast<int32_t *>(ws + L.tables); }
+    void *d_pop(int k) { return ws + L.pop[k]; }
+    double *d_part1() { return reinterpret_cast<double *>(ws + L.part1); }
+    double *d_part3() { return reinterpret_cast<double *>(ws + L.part3); }
+    double *d_raw() { return reinterpret_cast<double *>(ws + L.raw); }
+    double *d_vrho() { return reinterpret_cast<double *>(ws + L.vrho); }
+    uint8_t *d_flags() { return reinterpret_cast<uint8_t *>(ws + L.flags); }
+    double *d_series() { return reinterpret_cast<double *>(ws + L.series); }
+    double *d_aux() { return reinterpret_cast<double *>(ws + L.aux); }
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int code, const std::string &m) {
+    if (c) c->err = m;
+    else g_init_error = m;
+    return code;
+}
+
+int hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
+    return fail(c, LBM_EDEVICE, fmt("%s: %s", what, hipGetErrorString(e)));
+}
+
+#define HIP_TRY(c, call)                                                                           \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call);                                     \
+    } while (0)
+
+// tiling of the main kernel and the workgroup tables
+void build_tiling(lbm_ctx *c) {
+    const int n = c->nrep;
+    c->tables.assign(3 * (n + 1), 0);
+    int32_t *wg_begin = c->tables.data(), *k3_begin = wg_begin + (n + 1), *init_begin = k3_begin + (n + 1);
+    int wg = 0, k3 = 0, iw = 0;
+    size_t lds_elems = 0;
+    for (int r = 0; r < n; r++) {
+        RepDesc &D = c->desc[r];
+        const lbm_params &q = c->p[r];
+        D.ty = std::max(1, std::min(q.ny, c->block / q.nx));
+        D.nty = (q.ny + D.ty - 1) / D.ty;
+        D.cz = std::min(c->cz, q.nz);
+        D.nchunk = (q.nz + D.cz - 1) / D.cz;
+        D.wg_begin = wg;
+        wg_begin[r] = wg;
+        wg += D.nty * D.nchunk;
+        D.k3_begin = k3;
+        k3_begin[r] = k3;
+        D.k3_count = c->L.k3_count[r];
+        k3 += D.k3_count;
+        init_begin[r] = iw;
+        iw += (int)c->L.init_wg[r];
+        lds_elems = std::max(lds_elems, (size_t)6 * (D.ty + 2) * q.nx);
+    }
+    wg_begin[n] = wg;
+    k3_begin[n] = k3;
+    init_begin[n] = iw;
+    c->main_grid = wg;
+    c->k3_grid = k3;
+    c->init_grid = iw;
+    c->lds = lds_elems * (c->prec == LBM_FP64 ? 8 : 4);
+}
+
+int upload_desc(lbm_ctx *c) {
+    HIP_TRY(c, hipMemcpyAsync(c->d_desc(), c->desc.data(), sizeof(RepDesc) * c->nrep,
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_tables(), c->tables.data(), sizeof(int32_t) * c->tables.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+void drop_graph(lbm_ctx *c) {
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_parity = -1;
+}
+
+int enqueue_step(lbm_ctx *c, bool timed) {
+    MainArgs m;
+    m.desc = c->d_desc();
+    m.state = c->d_state();
+    m.wg_begin = c->d_tables();
+    m.nrep = c->nrep;
+    m.src = c->d_pop(c->cur);
+    m.dst = c->d_pop(1 - c->cur);
+    m.part1 = c->d_part1();
+    m.vrho = c->d_vrho();
+    m.tau1 = c->tau1;
+    if (timed) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int k = 0; k < 256; k++) {
+                hipEvent_t e;
+                HIP_TRY(c, hipEventCreate(&e));
+                c->ev.push_back(e);
+            }
+        }
+        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    }
+    hipError_t e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "main kernel launch");
+    if (timed) {
+        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
+    ParticleArgs pa;
+    pa.desc = c->d_desc();
+    pa.state = c->d_state();
+    pa.k3_begin = c->d_tables() + (c->nrep + 1);
+    pa.nrep = c->nrep;
+    pa.buf = c->d_pop(1 - c->cur);
+    pa.part1 = c->d_part1();
+    pa.part3 = c->d_part3();
+    pa.raw = c->d_raw();
+    pa.flags = c->d_flags();
+    pa.vrho = c->d_vrho();
+    pa.series = c->d_series();
+    e = launch_particle(c->prec, pa, c->k3_grid, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "particle kernel launch");
+    c->cur = 1 - c->cur;
+    return LBM_OK;
+}
+
+int check_rep(lbm_ctx *c, int r) {
+    if (!c) return LBM_EINVAL;
+    if (r < 0 || r >= c->nrep) return fail(c, LBM_EINVAL, fmt("replica %d out of range", r));
+    return LBM_OK;
+}
+
+int read_state(lbm_ctx *c, int r, RepState *s) {
+    HIP_TRY(c, hipMemcpyAsync(s, c->d_state() + r, sizeof(RepState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+#define LBM_API __attribute__((visibility("default")))
+
+LBM_API int lbm_workspace_bytes(const lbm_params *p, int32_t n_replicas, int32_t precision, size_t *bytes) {
+    const std::string v = validate(p, n_replicas, precision);
+    if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
+    if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+    *bytes = plan(p, n_replicas, precision).total;
+    return LBM_OK;
+}
+
+LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision, void *dev_ws,
+             size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    const std::string v = validate(p, n_replicas, precision);
+    if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
+    if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
+        return fail(nullptr, LBM_ENOMEM, "workspace must be a 256-byte aligned device pointer");
+    Layout L = plan(p, n_replicas, precision);
+    if (ws_bytes < L.total)
+        return fail(nullptr, LBM_ENOMEM, fmt("workspace of %zu bytes is smaller than the %zu needed",
+                                             ws_bytes, L.total));
+    lbm_ctx *c = new lbm_ctx();
+    c->p.assign(p, p + n_replicas);
+    c->nrep = n_replicas;
+    c->prec = precision;
+    c->es = elem_size(precision);
+    c->ws = reinterpret_cast<char *>(dev_ws);
+    c->ws_bytes = ws_bytes;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->L = L;
+    c->desc.resize(n_replicas);
+    c->tau1 = 1;
+    std::vector<RepState> st(n_replicas);
+    for (int r = 0; r < n_replicas; r++) {
+        const lbm_params &q = p[r];
+        RepDesc &D = c->desc[r];
+        std::memset(&D, 0, sizeof(D));
+        D.nx = q.nx; D.ny = q.ny; D.nz = q.nz; D.walls = q.walls;
+        D.N = (int64_t)q.nx * q.ny * q.nz;
+        D.pop_off = L.pop_off[r];
+        D.S = L.S[r];
+        D.has_particle = has_sphere(q);
+        D.bbox_off = L.bbox_off[r];
+        D.part1_off = L.part1_off[r];
+        D.part3_off = L.part3_off[r];
+        D.series_off = L.series_off[r];
+        D.series_cap = q.series_cap;
+        D.rho0[0] = q.rho0[0]; D.rho0[1] = q.rho0[1];
+        D.G = q.G;
+        D.radius = D.has_particle ? q.radius : 0.0;
+        D.R2 = D.radius * D.radius;
+        D.rho_p = q.rho_p;
+        const double V = D.has_particle ? 4.0 / 3.0 * M_PI * q.radius * q.radius * q.radius : 0.0;
+        D.mp = q.rho_p * V;
+        D.Ip = 0.4 * D.mp * q.radius * q.radius;
+        D.drho = q.wet_drho;
+        D.tau[0] = q.tau_shear; D.tau[1] = q.tau_bulk; D.tau[2] = q.tau_mom; D.tau[3] = q.tau_ghost;
+        for (double t : D.tau)
+            if (t != 1.0) c->tau1 = 0;
+        D.kT = q.kT;
+        D.init_amp = q.init_amp;
+        D.key0 = (uint32_t)(q.seed & 0xffffffffu);
+        D.key1 = (uint32_t)(q.seed >> 32) ^ (uint32_t)q.replica;
+        D.noise_diffusive = q.noise_diffusive;
+        D.fixed_velocity = q.fixed_velocity;
+        RepState &s = st[r];
+        std::memset(&s, 0, sizeof(s));
+        for (int a = 0; a < 3; a++) {
+            s.X[a] = q.X0[a]; s.Xp[a] = q.X0[a];
+            s.U[a] = D.has_particle ? q.U0[a] : 0.0;
+            s.W[a] = D.has_particle ? q.W0[a] : 0.0;
+        }
+        s.local_read = 1;
+    }
+    build_tiling(c);
+    int rc = upload_desc(c);
+    if (rc != LBM_OK) { g_init_error = c->err; delete c; return rc; }
+    hipError_t e = hipMemcpyAsync(c->d_state(), st.data(), sizeof(RepState) * n_replicas,
+                                  hipMemcpyHostToDevice, c->stream);
+    InitArgs ia;
+    ia.desc = c->d_desc();
+    ia.state = c->d_state();
+    ia.init_begin = c->d_tables() + 2 * (n_replicas + 1);
+    ia.nrep = n_replicas;
+    ia.buf = c->d_pop(0);
+    ia.mass = c->d_aux();
+    ia.vrho = c->d_vrho();
+    if (e == hipSuccess) e = launch_init(precision, ia, c->init_grid, n_replicas, c->stream);
+    std::vector<double> mass(2 * L.init_tot);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(mass.data(), c->d_aux(), sizeof(double) * mass.size(),
+                           hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g_init_error = fmt("initialisation: %s", hipGetErrorString(e));
+        delete c;
+        return LBM_EDEVICE;
+    }
+    int64_t w = 0;
+    for (int r = 0; r < n_replicas; r++) {
+        const lbm_params &q = p[r];
+        RepDesc &D = c->desc[r];
+        double M = 0.0;
+        for (int64_t k = 0; k < L.init_wg[r]; k++, w++) M += mass[2 * w] + mass[2 * w + 1];
+        D.M0 = M;
+        const double V = D.has_particle ? 4.0 / 3.0 * M_PI * q.radius * q.radius * q.radius : 0.0;
+        const double rho_tot0 = q.rho0[0] + q.rho0[1];
+        for (int a = 0; a < 3; a++) {
+            if (q.force_mode == 1) {
+                D.af[a] = q.g[a];
+                D.Fext[a] = V * q.rho_p * q.g[a];
+            } else {
+                D.Fext[a] = V * (q.rho_p - rho_tot0) * q.g[a];
+                D.af[a] = M > 0.0 ? -D.Fext[a] / M : 0.0;
+            }
+        }
+    }
+    rc = upload_desc(c);
+    if (rc != LBM_OK) { g_init_error = c->err; delete c; return rc; }
+    c->cur = 0;
+    *out = c;
+    return LBM_OK;
+}
+
+LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    int32_t left = nsteps;
+    if (c->graph_steps > 0 && !c->timing) {
+        while (left >= c->graph_steps) {
+            if (!c->gexec || c->graph_parity != c->cur) {
+                drop_graph(c);
+                const int parity = c->cur;
+                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                int rc = LBM_OK;
+                for (int k = 0; k < c->graph_steps && rc == LBM_OK; k++) rc = enqueue_step(c, false);
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamEndCapture(c->stream, &graph);
+                c->cur = parity;  // capture only recorded the launches
+                if (rc != LBM_OK) { if (graph) hipGraphDestroy(graph); return rc; }
+                if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                if (e != hipSuccess) { c->gexec = nullptr; return hip_fail(c, e, "hipGraphInstantiate"); }
+                c->graph_parity = parity;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+            if (c->graph_steps % 2) c->cur = 1 - c->cur;
+            left -= c->graph_steps;
+        }
+    }
+    for (int32_t k = 0; k < left; k++) {
+        const int rc = enqueue_step(c, c->timing);
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_sync(lbm_ctx *c) {
+    if (!c) return LBM_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+LBM_API int lbm_particle_state(lbm_ctx *c, int32_t replica, lbm_particle *out) {
+    int rc = check_rep(c, replica);
+    if (rc != LBM_OK) return rc;
+    if (!out) return fail(c, LBM_EINVAL, "out is NULL");
+    RepState s;
+    rc = read_state(c, replica, &s);
+    if (rc != LBM_OK) return rc;
+    for (int a = 0; a < 3; a++) {
+        out->X[a] = s.X[a]; out->U[a] = s.U[a]; out->W[a] = s.W[a];
+        out->F[a] = s.F[a]; out->T[a] = s.T[a]; out->Pev[a] = s.Pev[a]; out->Lev[a] = s.Lev[a];
+    }
+    out->delta[0] = s.delta[0];
+    out->delta[1] = s.delta[1];
+    out->n_fluid = s.n_fluid;
+    out->step = s.step;
+    out->n_covered = s.n_cov;
+    out->n_uncovered = s.n_unc;
+    out->n_links = s.n_links;
+    if (s.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "run went unstable");
+    return LBM_OK;
+}
+
+LBM_API int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f) {
+    int rc = check_rep(c, replica);
+    if (rc != LBM_OK) return rc;
+    if (!host_f) return fail(c, LBM_EINVAL, "host_f is NULL");
+    const lbm_params &q = c->p[replica];
+    const int64_t plane = (int64_t)q.nx * q.ny, N = plane * q.nz;
+    const size_t cap = 38 * c->L.Ntot * c->es;  // the free population buffer is the scratch
+    int zs = (int)std::max<int64_t>(1, std::min<int64_t>(q.nz, cap / (38 * plane * sizeof(double))));
+    std::vector<double> host((size_t)38 * plane * zs);
+    for (int z0 = 0; z0 < q.nz; z0 += zs) {
+        const int z1 = std::min(q.nz, z0 + zs);
+        const int64_t cnt = plane * (z1 - z0);
+        ExportArgs a;
+        a.desc = c->d_desc();
+        a.state = c->d_state();
+        a.rep = replica;
+        a.z_begin = z0;
+        a.z_end = z1;
+        a.src = c->d_pop(c->cur);
+        a.out = reinterpret_cast<double *>(c->d_pop(1 - c->cur));
+        hipError_t e = launch_export(c->prec, a, cnt, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "export kernel launch");
+        HIP_TRY(c, hipMemcpyAsync(host.data(), a.out, sizeof(double) * 38 * cnt,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int k = 0; k < 38; k++)
+            std::memcpy(host_f + (int64_t)k * N + plane * z0, host.data() + (int64_t)k * cnt,
+                        sizeof(double) * cnt);
+    }
+    return LBM_OK;
+}
+
+namespace {
+int run_fields(lbm_ctx *c, int r, bool columns) {
+    const lbm_params &q = c->p[r];
+    const int64_t plane = (int64_t)q.nx * q.ny, N = plane * q.nz;
+    FieldArgs a;
+    a.desc = c->d_desc();
+    a.state = c->d_state();
+    a.rep = r;
+    a.src = c->d_pop(c->cur);
+    a.vrho = c->d_vrho();
+    a.scratch = reinterpret_cast<double *>(c->d_pop(1 - c->cur));
+    a.columns = columns ? c->d_aux() : nullptr;
+    hipError_t e = launch_fields(c->prec, a, N, plane, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field kernels launch");
+    return LBM_OK;
+}
+}  // namespace
+
+LBM_API int lbm_fields(lbm_ctx *c, int32_t replica, double *host_rho, double *host_u) {
+    int rc = check_rep(c, replica);
+    if (rc != LBM_OK) return rc;
+    if (!host_rho || !host_u) return fail(c, LBM_EINVAL, "output is NULL");
+    rc = run_fields(c, replica, false);
+    if (rc != LBM_OK) return rc;
+    const lbm_params &q = c->p[replica];
+    const int64_t N = (int64_t)q.nx * q.ny * q.nz;
+    const double *s = reinterpret_cast<const double *>(c->d_pop(1 - c->cur));
+    std::vector<double> sol(N);
+    HIP_TRY(c, hipMemcpyAsync(host_rho, s, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(host_u, s + 5 * N, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sol.data(), s + 8 * N, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t n = 0; n < N; n++)
+        if (sol[n] != 0.0) host_rho[n] = host_rho[N + n] = 0.0;
+    return LBM_OK;
+}
+
+LBM_API int lbm_observables(lbm_ctx *c, int32_t replica, lbm_obs *o) {
+    int rc = check_rep(c, replica);
+    if (rc != LBM_OK) return rc;
+    if (!o) return fail(c, LBM_EINVAL, "o is NULL");
+    rc = run_fields(c, replica, true);
+    if (rc != LBM_OK) return rc;
+    const lbm_params &q = c->p[replica];
+    const int64_t plane = (int64_t)q.nx * q.ny;
+    std::vector<double> col(8 * plane);
+    HIP_TRY(c, hipMemcpyAsync(col.data(), c->d_aux(), sizeof(double) * col.size(),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 8; k++)
+        for (int64_t i = 0; i < plane; i++) s[k] += col[k * plane + i];
+    o->mass[0] = s[0];
+    o->mass[1] = s[1];
+    for (int a = 0; a < 3; a++) o->momentum[a] = s[2 + a];
+    o->n_fluid = s[7];
+    o->u2_mean = s[7] > 0 ? s[5] / s[7] : 0.0;
+    o->uz_mean = s[7] > 0 ? s[6] / s[7] : 0.0;
+    if (o->uz_profile)
+        for (int64_t i = 0; i < plane; i++)
+            o->uz_profile[i] = col[7 * plane + i] > 0 ? col[6 * plane + i] / col[7 * plane + i] : 0.0;
+    RepState st;
+    rc = read_state(c, replica, &st);
+    if (rc != LBM_OK) return rc;
+    if (st.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "run went unstable");
+    return LBM_OK;
+}
+
+LBM_API int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t cap, int64_t *count) {
+    int rc = check_rep(c, replica);
+    if (rc != LBM_OK) return rc;
+    if (!host_u3 || !count || cap < 0) return fail(c, LBM_EINVAL, "bad output arguments");
+    RepState st;
+    rc = read_state(c, replica, &st);
+    if (rc != LBM_OK) return rc;
+    const int64_t ring = c->p[replica].series_cap;
+    const int64_t avail = std::min<int64_t>(st.step, ring);
+    const int64_t n = std::min<int64_t>(avail, cap);
+    std::vector<double> buf(3 * ring);
+    HIP_TRY(c, hipMemcpyAsync(buf.data(), c->d_series() + c->L.series_off[replica],
+                              sizeof(double) * 3 * ring, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t first = st.step - n;  // oldest step index returned
+    for (int64_t k = 0; k < n; k++) {
+        const int64_t slot = (first + k) % ring;
+        for (int a = 0; a < 3; a++) host_u3[3 * k + a] = buf[3 * slot + a];
+    }
+    *count = n;
+    return LBM_OK;
+}
+
+LBM_API int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = 38 * c->L.Ntot * c->es + sizeof(RepState) * c->nrep + sizeof(double) * 2 * c->L.S3tot;
+    return LBM_OK;
+}
+
+LBM_API int lbm_checkpoint(lbm_ctx *c, void *dev_dst) {
+    if (!c || !dev_dst) return LBM_EINVAL;
+    char *d = reinterpret_cast<char *>(dev_dst);
+    const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
+    HIP_TRY(c, hipMemcpyAsync(d, c->d_pop(c->cur), pb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d + pb, c->d_state(), sb, hipMemcpyDeviceToDevice, c->stream));
+    if (c->L.S3tot)
+        HIP_TRY(c, hipMemcpyAsync(d + pb + sb, c->d_vrho(), sizeof(double) * 2 * c->L.S3tot,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+LBM_API int lbm_restore(lbm_ctx *c, const void *dev_src) {
+    if (!c || !dev_src) return LBM_EINVAL;
+    const char *d = reinterpret_cast<const char *>(dev_src);
+    const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
+    HIP_TRY(c, hipMemcpyAsync(c->d_pop(c->cur), d, pb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_state(), d + pb, sb, hipMemcpyDeviceToDevice, c->stream));
+    if (c->L.S3tot)
+        HIP_TRY(c, hipMemcpyAsync(c->d_vrho(), d + pb + sb, sizeof(double) * 2 * c->L.S3tot,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk) {
+    if (!c) return LBM_EINVAL;
+    if (block != 256) return fail(c, LBM_EINVAL, "block must be 256");
+    if (zchunk < 1) return fail(c, LBM_EINVAL, "zchunk must be >= 1");
+    c->block = block;
+    c->cz = zchunk;
+    build_tiling(c);
+    drop_graph(c);
+    return upload_desc(c);
+}
+
+LBM_API int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk) {
+    if (!c || !block || !zchunk) return LBM_EINVAL;
+    *block = c->block;
+    *zchunk = c->cz;
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph) {
+    if (!c) return LBM_EINVAL;
+    if (steps_per_graph < 0) return fail(c, LBM_EINVAL, "steps_per_graph must be >= 0");
+    if (steps_per_graph > 0 && c->stream == nullptr)
+        return fail(c, LBM_EINVAL, "graph replay needs a non-default stream");
+    drop_graph(c);
+    c->graph_steps = steps_per_graph;
+    return LBM_OK;
+}
+
+LBM_API int lbm_timing(lbm_ctx *c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    return LBM_OK;
+}
+
+LBM_API int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count) {
+    if (!c || !mean_ms || !count) return LBM_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+        sum += ms;
+    }
+    *count = (int64_t)(c->ev_used / 2);
+    *mean_ms = *count ? sum / (double)*count : 0.0;
+    return LBM_OK;
+}
+
+LBM_API int lbm_step_bytes(lbm_ctx *c, double *bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = 2.0 * 38.0 * (double)c->L.Ntot * (double)c->es;
+    return LBM_OK;
+}
+
+LBM_API void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    drop_graph(c);
+    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    delete c;
+}
+
+LBM_API const char *lbm_last_error(const lbm_ctx *c) {
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

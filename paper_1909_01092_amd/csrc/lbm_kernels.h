@@ -1,0 +1,82 @@
+// Launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_types.h"
+
+namespace lbm {
+
+struct MainArgs {
+    const RepDesc *desc;
+    RepState *state;
+    const int32_t *wg_begin;   // nrep entries
+    int32_t nrep;
+    const void *src;           // populations of step n (post-collision of n-1)
+    void *dst;                 // post-collision populations of step n
+    double *part1;             // per-workgroup link partials
+    const double *vrho;        // wetting-layer densities of step n
+    int32_t tau1;              // every relaxation time of every replica is 1
+};
+
+struct ParticleArgs {
+    const RepDesc *desc;
+    RepState *state;
+    const int32_t *k3_begin;
+    int32_t nrep;
+    void *buf;                 // post-collision populations just written by k_main
+    const double *part1;
+    double *part3;
+    double *raw;
+    uint8_t *flags;
+    double *vrho;
+    double *series;
+};
+
+struct InitArgs {
+    const RepDesc *desc;
+    RepState *state;
+    const int32_t *init_begin;
+    int32_t nrep;
+    void *buf;
+    double *mass;              // 2 per init workgroup
+    double *vrho;
+};
+
+struct ExportArgs {
+    const RepDesc *desc;
+    const RepState *state;
+    int32_t rep;
+    int32_t z_begin, z_end;
+    const void *src;
+    double *out;
+};
+
+struct FieldArgs {
+    const RepDesc *desc;
+    const RepState *state;
+    int32_t rep;
+    const void *src;
+    const double *vrho;
+    double *scratch;           // 9 N doubles
+    double *columns;           // 8 nx ny doubles, or null
+};
+
+// dispatch on the storage precision (0 FP64, 1 FP32, 2 FP16)
+hipError_t launch_main(int prec, const MainArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_particle(int prec, const ParticleArgs &a, int grid, hipStream_t s);
+hipError_t launch_init(int prec, const InitArgs &a, int grid, int nrep, hipStream_t s);
+hipError_t launch_export(int prec, const ExportArgs &a, int64_t count, hipStream_t s);
+hipError_t launch_fields(int prec, const FieldArgs &a, int64_t N, int64_t plane, hipStream_t s);
+
+#define LBM_DECLARE(SUFFIX)                                                                        \
+    hipError_t launch_main_##SUFFIX(const MainArgs &, int, int, size_t, hipStream_t);              \
+    hipError_t launch_particle_##SUFFIX(const ParticleArgs &, int, hipStream_t);                   \
+    hipError_t launch_init_##SUFFIX(const InitArgs &, int, hipStream_t);                           \
+    hipError_t launch_export_##SUFFIX(const ExportArgs &, int64_t, hipStream_t);                   \
+    hipError_t launch_fields_a_##SUFFIX(const FieldArgs &, int64_t, hipStream_t);
+LBM_DECLARE(f64)
+LBM_DECLARE(f32)
+LBM_DECLARE(f16)
+
+}  // namespace lbm

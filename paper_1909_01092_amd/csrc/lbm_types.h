@@ -1,0 +1,64 @@
+// Device-side data layout of the library (workspace contents).
+//
+// Populations: two ping-pong buffers; replica r owns a block of 38 N_r
+// elements laid out [component][direction][z][y][x] (x fastest).  A buffer
+// holds the post-collision values f*_i(x) of the last step at their source
+// node (pull scheme); a value whose link ends in a wall or a particle node is
+// stored already bounced (moving-wall term applied).  Elements are stored as
+// deviations from w_i rho0_l (FP64, FP32) or as relative deviations
+// (f - w_i rho0_l) / (w_i rho0_l) (FP16).
+#pragma once
+#include <stdint.h>
+
+namespace lbm {
+
+struct RepDesc {
+    int32_t nx, ny, nz;
+    uint32_t walls;          // bit0 x, bit1 y, bit2 z
+    int64_t N;               // nodes
+    int64_t pop_off;         // element offset of the replica block in a population buffer
+    int32_t ty;              // rows (y) per main-kernel tile; tiles span full x rows
+    int32_t nty, nchunk;     // tiles along y, z-chunks
+    int32_t wg_begin;        // first main-kernel workgroup of this replica
+    int32_t k3_begin, k3_count;  // particle-kernel workgroups
+    int32_t S;               // edge of the particle bounding box (nodes)
+    int32_t has_particle;
+    int64_t bbox_off;        // element offset of this replica in the bbox arrays (S^3 each)
+    int64_t part1_off;       // double offset of main-kernel partials (16 per workgroup)
+    int64_t part3_off;       // double offset of particle-kernel partials (16 per workgroup)
+    int64_t series_off;      // double offset of the U series ring (3 per entry)
+    int32_t series_cap;
+    int32_t cz;              // z-chunk of the main kernel
+    double rho0[2];
+    double G;
+    double af[3];            // body-force acceleration of the fluid
+    double Fext[3];          // external force on the particle
+    double M0;               // initial fluid mass (balanced driving)
+    double radius, R2, rho_p, mp, Ip, drho;
+    double tau[4];           // shear, bulk, momentum, ghost
+    double kT;
+    double init_amp;
+    uint32_t key0, key1;
+    int32_t noise_diffusive, fixed_velocity;
+};
+
+struct RepState {
+    double X[3], Xp[3];      // X^n and X^{n-1}
+    double U[3], W[3];       // U^{n-1/2}, Omega^{n-1/2}
+    double F[3], T[3];       // total force / torque of the last step
+    double Pev[3], Lev[3];   // pending cover/uncover momentum, angular momentum
+    double delta[2];         // mass correction applied when pulling step n
+    double n_fluid;
+    double pad0;
+    int64_t step, n_cov, n_unc, n_links;
+    int32_t org[3];          // origin of the bbox arrays written for step n
+    int32_t local_read;      // 1: populations of step n sit in their own slots
+    uint32_t flags;          // bit0 unstable
+    uint32_t k3_done;        // particle-kernel completion counter
+    uint32_t pad1[2];
+};
+
+constexpr uint32_t FLAG_UNSTABLE = 1u;
+constexpr int PART = 16;     // doubles per workgroup partial
+
+}  // namespace lbm

@@ -1,0 +1,182 @@
+"""Simulation: a thin Python handle on the C ABI (include/lbm.h).
+
+PyTorch supplies the device workspace (one uint8 tensor) and the HIP stream;
+every step of the method runs in the library's HIP kernels.  The names follow
+the C calls: step, particle_state, observables, populations, fields,
+u_series, checkpoint / restore.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _capi
+from .workloads import full
+
+
+def _fill(p: _capi.LbmParams, q: dict):
+    for name, ctype in _capi.LbmParams._fields_:
+        if name == "reserved":
+            continue
+        v = q[name]
+        if hasattr(ctype, "_length_"):
+            setattr(p, name, ctype(*[float(x) for x in v]))
+        elif ctype in (C.c_double,):
+            setattr(p, name, float(v))
+        else:
+            setattr(p, name, int(v))
+
+
+def make_params(replicas) -> C.Array:
+    """ctypes array of lbm_params from one dict or a list of dicts."""
+    if isinstance(replicas, dict):
+        replicas = [replicas]
+    arr = (_capi.LbmParams * len(replicas))()
+    for k, q in enumerate(replicas):
+        _fill(arr[k], full(q))
+    return arr
+
+
+def workspace_bytes(replicas, precision="fp64") -> int:
+    arr = make_params(replicas)
+    n = C.c_size_t()
+    _capi.check(_capi.lib().lbm_workspace_bytes(arr, len(arr), _capi.PRECISIONS[precision],
+                                                C.byref(n)))
+    return n.value
+
+
+class Simulation:
+    """One or more replicas advanced together on one GPU."""
+
+    def __init__(self, replicas, precision: str = "fp64", device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Simulation needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.replicas = [full(q) for q in ([replicas] if isinstance(replicas, dict) else replicas)]
+        self.precision = precision
+        self.device = torch.device(device)
+        self._lib = _capi.lib()
+        self._params = make_params(self.replicas)
+        nbytes = workspace_bytes(self.replicas, precision)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        rc = self._lib.lbm_init(self._params, len(self._params), _capi.PRECISIONS[precision],
+                                C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                C.byref(ctx))
+        _capi.check(rc, None)
+        self._ctx = ctx
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        return _capi.check(rc, self._ctx)
+
+    # -- stepping
+    def step(self, n: int = 1):
+        self._check(self._lib.lbm_step(self._ctx, int(n)))
+
+    def sync(self):
+        self._check(self._lib.lbm_sync(self._ctx))
+
+    def set_launch(self, block: int = 256, zchunk: int = 8):
+        self._check(self._lib.lbm_set_launch(self._ctx, int(block), int(zchunk)))
+
+    def get_launch(self):
+        b, z = C.c_int32(), C.c_int32()
+        self._check(self._lib.lbm_get_launch(self._ctx, C.byref(b), C.byref(z)))
+        return b.value, z.value
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self._lib.lbm_set_graph(self._ctx, int(steps_per_graph)))
+
+    def timing(self, enable: bool):
+        self._check(self._lib.lbm_timing(self._ctx, int(bool(enable))))
+
+    def timing_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self._lib.lbm_timing_read(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def step_bytes(self) -> float:
+        b = C.c_double()
+        self._check(self._lib.lbm_step_bytes(self._ctx, C.byref(b)))
+        return b.value
+
+    # -- queries
+    def particle_state(self, replica: int = 0, allow_unstable: bool = False) -> dict:
+        P = _capi.LbmParticle()
+        rc = self._lib.lbm_particle_state(self._ctx, int(replica), C.byref(P))
+        if not (allow_unstable and rc == _capi.LBM_EUNSTABLE):
+            self._check(rc)
+        out = {}
+        for name, ctype in _capi.LbmParticle._fields_:
+            v = getattr(P, name)
+            out[name] = np.array(list(v)) if hasattr(ctype, "_length_") else v
+        out["unstable"] = rc == _capi.LBM_EUNSTABLE
+        return out
+
+    def _dims(self, r):
+        q = self.replicas[r]
+        return q["nx"], q["ny"], q["nz"]
+
+    def populations(self, replica: int = 0) -> np.ndarray:
+        nx, ny, nz = self._dims(replica)
+        f = np.empty((2, 19, nz, ny, nx), dtype=np.float64)
+        self._check(self._lib.lbm_populations(self._ctx, int(replica),
+                                              f.ctypes.data_as(C.POINTER(C.c_double))))
+        return f
+
+    def fields(self, replica: int = 0):
+        nx, ny, nz = self._dims(replica)
+        rho = np.empty((2, nz, ny, nx))
+        u = np.empty((3, nz, ny, nx))
+        self._check(self._lib.lbm_fields(self._ctx, int(replica),
+                                         rho.ctypes.data_as(C.POINTER(C.c_double)),
+                                         u.ctypes.data_as(C.POINTER(C.c_double))))
+        return rho, u
+
+    def observables(self, replica: int = 0, profile: bool = False) -> dict:
+        nx, ny, nz = self._dims(replica)
+        o = _capi.LbmObs()
+        prof = np.zeros((ny, nx)) if profile else None
+        o.uz_profile = prof.ctypes.data_as(C.POINTER(C.c_double)) if profile else None
+        self._check(self._lib.lbm_observables(self._ctx, int(replica), C.byref(o)))
+        out = dict(mass=np.array(list(o.mass)), momentum=np.array(list(o.momentum)),
+                   u2_mean=o.u2_mean, uz_mean=o.uz_mean, n_fluid=o.n_fluid)
+        if profile:
+            out["uz_profile"] = prof
+        return out
+
+    def u_series(self, replica: int = 0) -> np.ndarray:
+        cap = int(self.replicas[replica]["series_cap"])
+        buf = np.empty((cap, 3))
+        n = C.c_int64()
+        self._check(self._lib.lbm_u_series(self._ctx, int(replica),
+                                           buf.ctypes.data_as(C.POINTER(C.c_double)), cap,
+                                           C.byref(n)))
+        return buf[: n.value].copy()
+
+    # -- checkpoints (device tensors)
+    def checkpoint(self):
+        import torch
+        n = C.c_size_t()
+        self._check(self._lib.lbm_checkpoint_bytes(self._ctx, C.byref(n)))
+        t = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._check(self._lib.lbm_checkpoint(self._ctx, C.c_void_p(t.data_ptr())))
+        return t
+
+    def restore(self, t):
+        self._check(self._lib.lbm_restore(self._ctx, C.c_void_p(t.data_ptr())))

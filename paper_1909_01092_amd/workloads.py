@@ -1,0 +1,64 @@
+"""Run parameters and named workloads (plain data: no arithmetic of the method).
+
+A parameter set is a dict with the fields of lbm_params; missing fields take
+DEFAULTS.  The named workloads are the synthetic channels used for parity
+tests and benchmarks; they stand in for the paper's 60 x 60 x 900 closed
+channel (Sec. 3) at the sizes of each form of the hot path.
+"""
+
+DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.0,
+                tau_shear=1.0, tau_bulk=1.0, tau_mom=1.0, tau_ghost=1.0, kT=0.0, seed=0,
+                replica=0, g=(0.0, 0.0, 0.0), force_mode=0, radius=0.0, rho_p=2.0,
+                wet_drho=0.0, X0=None, U0=(0.0, 0.0, 0.0), W0=(0.0, 0.0, 0.0),
+                noise_diffusive=1, fixed_velocity=0, series_cap=4096)
+
+
+def full(params: dict) -> dict:
+    """Parameters with defaults filled in; X0 defaults to the box centre."""
+    q = dict(DEFAULTS)
+    q.update(params)
+    if q["X0"] is None:
+        q["X0"] = ((q["nx"] - 1) / 2.0, (q["ny"] - 1) / 2.0, (q["nz"] - 1) / 2.0)
+    return q
+
+
+def channel(n: int, nz: int, **kw) -> dict:
+    """Square n x n channel (walls in x and y, periodic z), sphere at the centre,
+    mixture 0.95 / 0.05 with +-1e-3 initial density noise, G = 1.5, tau = 1."""
+    p = dict(nx=n, ny=n, nz=nz, walls=3, rho0=(0.95, 0.05), init_amp=1e-3, G=1.5, rho_p=2.0)
+    p.update(kw)
+    return full(p)
+
+
+# FP64 parity case: 24 x 24 x 48, kT = 1e-5, R = 4, g = 1e-5 along z, 200 steps
+PARITY_SMALL = channel(24, 48, kT=1e-5, radius=4.0, g=(0.0, 0.0, 1e-5), seed=0)
+PARITY_SMALL_STEPS = 200
+
+# single run, FP32 deviations: 64 x 64 x 256, R = 8, kT = 1e-5, g = 1e-4 (timed point)
+SINGLE_RUN = channel(64, 256, kT=1e-5, radius=8.0, g=(0.0, 0.0, 1e-4), seed=1, series_cap=16384)
+SINGLE_RUN_STEPS = 10000
+
+
+def ensemble(steps_cap: int = 8192) -> list:
+    """128 replicas of 32x32x128 (R = 4), 32 of 24x24x96 (R = 3), 32 of 48x48x192
+    (R = 6); kT = 1e-5, g = 5e-5; independent Philox keys per replica."""
+    reps = []
+    for k in range(128):
+        reps.append(channel(32, 128, kT=1e-5, radius=4.0, g=(0, 0, 5e-5), seed=7, replica=k,
+                            series_cap=steps_cap))
+    for k in range(32):
+        reps.append(channel(24, 96, kT=1e-5, radius=3.0, g=(0, 0, 5e-5), seed=7, replica=128 + k,
+                            series_cap=steps_cap))
+    for k in range(32):
+        reps.append(channel(48, 192, kT=1e-5, radius=6.0, g=(0, 0, 5e-5), seed=7, replica=160 + k,
+                            series_cap=steps_cap))
+    return reps
+
+
+# adjoint form: 48 x 48 x 192, R = 6, kT = 1e-5, g = 5e-5
+ADJOINT = channel(48, 192, kT=1e-5, radius=6.0, g=(0.0, 0.0, 5e-5), seed=3)
+
+# large single run, FP16 relative deviations: 192 x 192 x 1024, R = 16, kT = 1e-4, g = 1e-4
+LARGE = channel(192, 192, kT=1e-4, radius=16.0, g=(0.0, 0.0, 1e-4), seed=5)
+LARGE["nz"] = 1024
+LARGE = full(dict(LARGE, X0=None))

@@ -1,0 +1,90 @@
+"""C ABI of the HIP library, checked without a GPU: the library loads, exports
+exactly the entry points include/lbm.h declares, and rejects invalid
+configurations before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_1909_01092_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_1909_01092_amd import build
+        build.build()
+    return _capi
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_match_header(capi):
+    out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert exported == header_functions()
+    assert sorted(capi.SIGNATURES) == header_functions()
+    capi.lib()  # every symbol resolves with its declared signature
+
+
+def test_struct_sizes_match_header(capi, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "lbm.h"\n#include <stdio.h>\nint main(void){printf("%zu %zu %zu\\n",'
+                   ' sizeof(lbm_params), sizeof(lbm_particle), sizeof(lbm_obs));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    sizes = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    assert sizes == [C.sizeof(capi.LbmParams), C.sizeof(capi.LbmParticle), C.sizeof(capi.LbmObs)]
+
+
+def _bytes(capi, params, prec="fp32"):
+    from paper_1909_01092_amd.sim import workspace_bytes
+    return workspace_bytes(params, prec)
+
+
+def test_workspace_sizes(capi):
+    from paper_1909_01092_amd import workloads as w
+    one = _bytes(capi, w.SINGLE_RUN, "fp32")
+    assert one >= 2 * 38 * 64 * 64 * 256 * 4
+    assert _bytes(capi, w.SINGLE_RUN, "fp16") < one < _bytes(capi, w.SINGLE_RUN, "fp64")
+    two = _bytes(capi, [w.SINGLE_RUN, w.SINGLE_RUN], "fp32")
+    assert two >= 2 * 38 * 2 * 64 * 64 * 256 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(nx=300), dict(tau_shear=0.5), dict(kT=-1.0), dict(rho0=(1.0, 0.0)),
+    dict(force_mode=3), dict(series_cap=0), dict(walls=9), dict(init_amp=0.2),
+    dict(nx=16, ny=16, nz=16, walls=3, radius=7.5),           # sphere touches a wall
+    dict(nx=12, ny=12, nz=12, radius=3.0),                    # periodic box too short for the bbox
+    dict(nx=16, ny=16, nz=32, walls=3, radius=3.0, U0=(0.0, 0.0, 0.6)),
+])
+def test_invalid_parameters_rejected(capi, bad):
+    from paper_1909_01092_amd.sim import workspace_bytes
+    q = dict(nx=16, ny=16, nz=16)
+    q.update(bad)
+    with pytest.raises(capi.LbmError) as e:
+        workspace_bytes(q, "fp32")
+    assert e.value.code == capi.LBM_EINVAL
+
+
+def test_init_rejects_bad_workspace_before_device_work(capi):
+    from paper_1909_01092_amd.sim import make_params, workspace_bytes
+    q = dict(nx=16, ny=16, nz=16)
+    arr = make_params(q)
+    need = workspace_bytes(q, "fp32")
+    ctx = C.c_void_p()
+    L = capi.lib()
+    assert L.lbm_init(arr, 1, 1, C.c_void_p(4096 + 8), need, None, C.byref(ctx)) == capi.LBM_ENOMEM
+    assert b"aligned" in L.lbm_last_error(None)
+    assert L.lbm_init(arr, 1, 1, C.c_void_p(4096), need - 1, None, C.byref(ctx)) == capi.LBM_ENOMEM
+    assert L.lbm_init(arr, 1, 7, C.c_void_p(4096), need, None, C.byref(ctx)) == capi.LBM_EINVAL
+    assert not ctx.value

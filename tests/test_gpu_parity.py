@@ -1,0 +1,234 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Tolerances (written here, derived in the design notes):
+  * FP64 storage: max |f_gpu - f_ref| / max |f_ref| < 1e-12 after 200 steps
+    (only the rounding order differs; every decision uses the same FP64
+    predicate);
+  * FP32 storage of deviations: max |d_gpu - d_ref| / max |d_ref| < 1e-5 per
+    field after 200 steps, with d = f - w_i rho0_l;
+  * FP16 relative-deviation storage: error reported, bounded loosely.
+Cases span several workgroup tiles and z-chunks with ragged tails, walls and
+periodic axes, with and without the sphere, with cover/uncover events.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_1909_01092_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_01092_amd.sim import Simulation
+    return Simulation
+
+
+def dev(f, rho0):
+    return f - W[None, :, None, None, None] * np.array(rho0)[:, None, None, None, None]
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def solid_mask(f):
+    return f.sum(axis=(0, 1)) == 0
+
+
+def compare(sim, ref, tol, tol_dev=None, rep=0, what=""):
+    f, fr = sim.populations(rep), ref.populations()
+    assert np.array_equal(solid_mask(f), solid_mask(fr)), f"{what}: particle nodes differ"
+    e = rel(f, fr)
+    rho0 = ref.params.get("rho0", (0.95, 0.05))
+    ed = rel(dev(f, rho0), dev(fr, rho0))
+    print(f"{what}: rel err f {e:.3e}, deviations {ed:.3e}", flush=True)
+    assert e < tol, (what, e)
+    if tol_dev is not None:
+        assert ed < tol_dev, (what, ed)
+    return e, ed
+
+
+def compare_particle(sim, ref, tol, rep=0, what=""):
+    pg, po = sim.particle_state(rep), ref.particle()
+    assert pg["step"] == po["step"]
+    assert pg["n_covered"] == po["n_covered"] and pg["n_uncovered"] == po["n_uncovered"], what
+    for k in ("X", "U", "W", "F", "T"):
+        scale = max(np.abs(po[k]).max(), 1e-300)
+        err = np.abs(pg[k] - po[k]).max() / scale
+        if k == "X":
+            err = np.abs(pg[k] - po[k]).max()
+        print(f"{what}: particle {k} err {err:.3e}", flush=True)
+        assert err < tol, (what, k, err)
+    return pg, po
+
+
+def test_initial_state(Sim):
+    p = workloads.channel(20, 18, kT=1e-5, radius=4.0, seed=9)
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    compare(sim, ref, 1e-15, 1e-12, what="init")
+    compare_particle(sim, ref, 1e-15, what="init")
+
+
+@pytest.mark.parametrize("walls,kT,G", [(3, 1e-5, 1.5), (0, 1e-4, 0.0), (7, 1e-5, 1.5)])
+def test_fluid_fp64(Sim, walls, kT, G):
+    p = workloads.full(dict(nx=16, ny=12, nz=21, walls=walls, kT=kT, G=G, init_amp=1e-3,
+                            g=(1e-5, 0.0, 2e-5), force_mode=1, seed=4))
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.set_launch(256, 8)       # 3 z-chunks, the last one ragged
+    for n in (1, 4, 25):
+        sim.step(n)
+        ref.step(n)
+        compare(sim, ref, 1e-13, 1e-9, what=f"fluid walls={walls} kT={kT} after +{n}")
+
+
+def test_sphere_fp64_parity_small_channel(Sim):
+    """24 x 24 x 48 channel, R = 4, kT = 1e-5, g = 1e-5, 200 steps (FP64)."""
+    p = workloads.PARITY_SMALL
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    for n in (1, 9, 40, 150):
+        sim.step(n)
+        ref.step(n)
+        compare(sim, ref, 1e-12, what=f"sphere after +{n}")
+    compare_particle(sim, ref, 1e-9, what="sphere 200 steps")
+    pg = sim.particle_state()
+    print(f"events: covered {pg['n_covered']} uncovered {pg['n_uncovered']}", flush=True)
+
+
+def test_events_prescribed_motion_fp64(Sim):
+    """A sphere driven at a prescribed velocity sweeps nodes: cover and uncover
+    events every few steps, with wetting and noise."""
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.3, wet_drho=0.2, fixed_velocity=1,
+                          U0=(0.01, -0.02, 0.07), W0=(0.0, 0.01, 0.0), seed=5)
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    for n in (3, 17, 40):
+        sim.step(n)
+        ref.step(n)
+        compare(sim, ref, 1e-12, what=f"events +{n}")
+        compare_particle(sim, ref, 1e-9, what=f"events +{n}")
+    assert sim.particle_state()["n_covered"] > 10
+
+
+def test_free_sphere_periodic_fp64(Sim):
+    p = workloads.full(dict(nx=14, ny=14, nz=15, walls=0, G=1.5, kT=1e-5, init_amp=1e-3,
+                            radius=2.5, wet_drho=0.1, U0=(0.02, -0.03, 0.05), seed=6))
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.step(60)
+    ref.step(60)
+    compare(sim, ref, 1e-12, what="periodic free sphere")
+    compare_particle(sim, ref, 1e-9, what="periodic free sphere")
+
+
+def test_fp32_parity_small_channel(Sim):
+    p = workloads.PARITY_SMALL
+    sim, ref = Sim(p, "fp32"), OracleSim(p)
+    sim.step(200)
+    ref.step(200)
+    compare(sim, ref, 1e-6, 1e-5, what="fp32 200 steps")
+    pg, po = sim.particle_state(), ref.particle()
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    errX = np.abs(pg["X"] - po["X"]).max()
+    print(f"fp32 particle U rel err {errU:.3e}, X abs err {errX:.3e}", flush=True)
+    assert errU < 1e-5 and errX < 1e-7
+
+
+def test_fp16_error_reported(Sim):
+    p = workloads.PARITY_SMALL
+    sim, ref = Sim(p, "fp16"), OracleSim(p)
+    sim.step(50)
+    ref.step(50)
+    e, ed = compare(sim, ref, 1e-3, what="fp16 50 steps")
+    assert ed < 5e-2
+
+
+def test_checkpoint_resume_bitwise(Sim):
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.3, wet_drho=0.2, fixed_velocity=1,
+                          U0=(0.01, -0.02, 0.07), seed=5)
+    a = Sim(p, "fp32")
+    a.step(10)
+    ck = a.checkpoint()
+    a.step(30)
+    fa, pa = a.populations(), a.particle_state()
+    a.restore(ck)
+    a.step(30)
+    fb, pb = a.populations(), a.particle_state()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(pa["X"], pb["X"]) and np.array_equal(pa["U"], pb["U"])
+
+
+def test_graph_replay_equals_plain_launches(Sim):
+    import torch
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 1e-4), seed=8)
+    s = torch.cuda.Stream()
+    a = Sim(p, "fp32", stream=s)
+    b = Sim(p, "fp32", stream=s)
+    b.set_graph(4)
+    for _ in range(3):
+        a.step(9)
+        b.step(9)
+        fa, fb = a.populations(), b.populations()
+        assert np.array_equal(fa, fb)
+        assert np.array_equal(a.particle_state()["U"], b.particle_state()["U"])
+
+
+def test_fields_and_observables(Sim):
+    p = workloads.channel(16, 20, kT=1e-5, radius=3.0, g=(0, 0, 1e-4), wet_drho=0.1, seed=2)
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.step(12)
+    ref.step(12)
+    rho, u = sim.fields()
+    rr, ur = ref.fields()
+    assert rel(rho, rr) < 1e-12
+    assert np.abs(u - ur).max() < 1e-12 * max(np.abs(ur).max(), 1e-6)
+    o = sim.observables(profile=True)
+    m, j = ref.observables()
+    assert np.abs(o["mass"] / m - 1).max() < 1e-12
+    assert np.abs(o["momentum"] - j).max() < 1e-10 * np.abs(m).sum()
+    fl = rr.sum(0) > 0
+    assert o["n_fluid"] == fl.sum()
+    assert abs(o["u2_mean"] - (ur ** 2).sum(0)[fl].mean()) < 1e-10 * (ur ** 2).sum(0)[fl].mean()
+
+
+def test_ensemble_of_uneven_replicas(Sim):
+    reps = [workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 5e-5), seed=7, replica=0),
+            workloads.channel(14, 20, kT=1e-5, radius=2.5, g=(0, 0, 5e-5), seed=7, replica=1),
+            workloads.full(dict(nx=12, ny=10, nz=18, walls=3, kT=1e-5, init_amp=1e-3, G=1.5,
+                                seed=7, replica=2))]
+    sim = Sim(reps, "fp64")
+    refs = [OracleSim(q) for q in reps]
+    sim.step(25)
+    for k, r in enumerate(refs):
+        r.step(25)
+        compare(sim, r, 1e-12, rep=k, what=f"ensemble replica {k}")
+
+
+def test_launch_shape_does_not_change_results(Sim):
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.3, seed=11)
+    a, b = Sim(p, "fp64"), Sim(p, "fp64")
+    a.set_launch(256, 3)
+    b.set_launch(256, 24)
+    a.step(20)
+    b.step(20)
+    assert rel(a.populations(), b.populations()) < 1e-14
+
+
+def test_single_run_full_size_one_step_fp32(Sim):
+    """64 x 64 x 256, R = 8, FP32 storage, in the benchmark's launch shape: the
+    GPU state after 30 steps is handed to the oracle, which takes one step;
+    the GPU's next step must agree to the FP32 tolerance."""
+    p = workloads.SINGLE_RUN
+    sim = Sim(p, "fp32")
+    sim.step(30)
+    f0, p0 = sim.populations(), sim.particle_state()
+    ref = OracleSim(p)
+    ref.set_populations(f0)
+    ref.set_particle({k: p0[k] for k in ("X", "U", "W", "Pev", "Lev", "step", "n_fluid")})
+    sim.step(1)
+    ref.step(1)
+    compare(sim, ref, 1e-7, 2e-5, what="64x64x256 one step from the GPU state")
