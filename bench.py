@@ -1,0 +1,160 @@
+"""Throughput of the fluctuating two-component D3Q19 + sphere step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|ensemble|large|parity]
+
+Prints ONE JSON line: MLUPS (replica node updates per second / 1e6, both
+components of a node counted once) for the chosen workload with all inputs
+resident in HBM, plus
+  roofline:     the main kernel's algorithmic HBM bytes per launch (read +
+                write of 2 x 19 populations per node) over its mean duration,
+                measured with HIP events on the library stream during the
+                timed region, against the 8 TB/s HBM peak;
+  cpu_baseline: the FP64 CPU oracle timed on a bounded sample of the same
+                workload on this host (single thread).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1909_01092_amd/csrc/lbm_kernels_impl.h",
+                  "paper_1909_01092_amd/csrc/lbm_math.h",
+                  "paper_1909_01092_amd/csrc/lbm_types.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    from paper_1909_01092_amd import workloads as w
+    if name == "single":
+        return ([w.SINGLE_RUN], "fp32", "single run 64x64x256 channel, FP32 deviation storage, "
+                "R=8, kT=1e-5, g=1e-4, G=1.5, tau=1")
+    if name == "ensemble":
+        return (w.ensemble(), "fp32", "ensemble 128x(32x32x128,R=4)+32x(24x24x96,R=3)+"
+                "32x(48x48x192,R=6), FP32 deviations, kT=1e-5, g=5e-5")
+    if name == "large":
+        return ([w.LARGE], "fp16", "large single run 192x192x1024, FP16 relative deviations, "
+                "R=16, kT=1e-4, g=1e-4")
+    if name == "parity":
+        return ([w.PARITY_SMALL], "fp64", "parity channel 24x24x48, FP64, R=4, kT=1e-5")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile(name, nbytes_alg):
+    """HBM bytes per launch of the main kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_main_{name}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(reps, budget_s=15.0):
+    """FP64 oracle on the first replica of the workload, whole steps until the
+    budget is spent (at least one step)."""
+    from oracle.oracle import OracleSim
+    p = reps[0]
+    t0 = time.perf_counter()
+    sim = OracleSim(p)
+    t_init = time.perf_counter() - t0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or el / steps * (steps + 1) > 2 * budget_s:
+            break
+    N = p["nx"] * p["ny"] * p["nz"]
+    return {"value": round(N * steps / el / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of one {p['nx']}x{p['ny']}x{p['nz']} replica of the same "
+                      f"workload in FP64 ({el:.1f} s; init {t_init:.1f} s excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="single")
+    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the hot path is one GPU's share); "
+              "multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1909_01092_amd.sim import Simulation
+    reps, prec, desc = workload(args.workload)
+    stream = torch.cuda.Stream()
+    sim = Simulation(reps, precision=prec, device="cuda:0", stream=stream)
+    if args.zchunk:
+        sim.set_launch(256, args.zchunk)
+    block, cz = sim.get_launch()
+    if args.graph:
+        sim.set_graph(args.graph)
+    sim.step(args.warmup)
+    sim.sync()
+
+    nodes = sum(q["nx"] * q["ny"] * q["nz"] for q in reps)
+    timed = not args.graph
+    sim.timing(timed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern_ms, nlaunch = sim.timing_read() if timed else (None, 0)
+    sim.timing(False)
+
+    state = [sim.particle_state(r, allow_unstable=True) for r in range(len(reps))]
+    unstable = any(s["unstable"] for s in state)
+    mlups = nodes * args.steps / el / 1e6
+    step_bytes = sim.step_bytes()
+    roof = None
+    if kern_ms:
+        achieved = step_bytes / (kern_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(args.workload, step_bytes),
+                "kernel": "k_main", "kernel_ms": round(kern_ms, 5), "launches": nlaunch,
+                "bytes_per_launch": step_bytes}
+    out = {
+        "metric": "MLUPS (2-comp D3Q19)", "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32"}[prec], "data": "synthetic",
+        "config": {"workload": desc, "replicas": len(reps), "nodes": nodes, "precision": prec,
+                   "block": block, "zchunk": cz, "graph_steps": args.graph,
+                   "unstable": unstable},
+        "roofline": roof,
+    }
+    sim.close()
+    del sim
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(reps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

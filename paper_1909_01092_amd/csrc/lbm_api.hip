@@ -37,23 +37,18 @@ int bbox_edge(const lbm_params &p) {
 }
 
 struct Layout {
-    size_t tables, desc, state, pop[2], part1, part3, raw, vrho, flags, series, aux, total;
-    std::vector<int64_t> pop_off, bbox_off, part1_off, part3_off, series_off, init_wg;
+    size_t tables, desc, state, pop[2], part1, part3, part3b, raw, vrho, rho_n, pmask, flags, series, aux,
+        total;
+    std::vector<int64_t> pop_off, bbox_off, part3_off, series_off, init_wg;
     std::vector<int> S, k3_count;
-    int64_t Ntot = 0, S3tot = 0, part1_tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
+    int64_t Ntot = 0, S3tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
     size_t aux_doubles = 0;
 };
-
-// largest main-kernel tile count a replica can need (one row, one plane)
-int64_t max_tiles(const lbm_params &p) {
-    const int ty = std::max(1, std::min(p.ny, MAIN_BLOCK_MIN / p.nx));
-    return (int64_t)((p.ny + ty - 1) / ty) * p.nz;
-}
 
 Layout plan(const lbm_params *p, int n, int prec) {
     Layout L;
     const size_t es = elem_size(prec);
-    L.pop_off.resize(n); L.bbox_off.resize(n); L.part1_off.resize(n); L.part3_off.resize(n);
+    L.pop_off.resize(n); L.bbox_off.resize(n); L.part3_off.resize(n);
     L.series_off.resize(n); L.S.resize(n); L.k3_count.resize(n); L.init_wg.resize(n);
     size_t max_cols = 0;
     for (int r = 0; r < n; r++) {
@@ -64,8 +59,6 @@ Layout plan(const lbm_params *p, int n, int prec) {
         const int64_t S3 = (int64_t)L.S[r] * L.S[r] * L.S[r];
         L.bbox_off[r] = L.S3tot;
         L.S3tot += S3;
-        L.part1_off[r] = L.part1_tot;
-        L.part1_tot += has_sphere(p[r]) ? max_tiles(p[r]) * PART : 0;
         L.k3_count[r] = has_sphere(p[r]) ? (int)((S3 + K3_BLOCK - 1) / K3_BLOCK) : 1;
         L.part3_off[r] = L.part3_tot;
         L.part3_tot += (int64_t)L.k3_count[r] * PART;
@@ -83,10 +76,13 @@ Layout plan(const lbm_params *p, int n, int prec) {
     L.state = take(sizeof(RepState) * n);
     L.pop[0] = take(38 * L.Ntot * es);
     L.pop[1] = take(38 * L.Ntot * es);
-    L.part1 = take(sizeof(double) * std::max<int64_t>(L.part1_tot, 1));
+    L.part1 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
     L.part3 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
+    L.part3b = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
     L.raw = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
     L.vrho = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
+    L.rho_n = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
+    L.pmask = take(sizeof(uint32_t) * std::max<int64_t>(L.S3tot, 1));
     L.flags = take(std::max<int64_t>(L.S3tot, 1));
     L.series = take(sizeof(double) * std::max<int64_t>(L.series_tot, 1));
     L.aux = take(sizeof(double) * L.aux_doubles);
@@ -178,8 +174,11 @@ struct lbm_ctx {
     void *d_pop(int k) { return ws + L.pop[k]; }
     double *d_part1() { return reinterpret_cast<double *>(ws + L.part1); }
     double *d_part3() { return reinterpret_cast<double *>(ws + L.part3); }
+    double *d_part3b() { return reinterpret_cast<double *>(ws + L.part3b); }
     double *d_raw() { return reinterpret_cast<double *>(ws + L.raw); }
     double *d_vrho() { return reinterpret_cast<double *>(ws + L.vrho); }
+    double *d_rho_n() { return reinterpret_cast<double *>(ws + L.rho_n); }
+    uint32_t *d_pmask() { return reinterpret_cast<uint32_t *>(ws + L.pmask); }
     uint8_t *d_flags() { return reinterpret_cast<uint8_t *>(ws + L.flags); }
     double *d_series() { return reinterpret_cast<double *>(ws + L.series); }
     double *d_aux() { return reinterpret_cast<double *>(ws + L.aux); }
@@ -260,8 +259,9 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     m.nrep = c->nrep;
     m.src = c->d_pop(c->cur);
     m.dst = c->d_pop(1 - c->cur);
-    m.part1 = c->d_part1();
+    m.pmask = c->d_pmask();
     m.vrho = c->d_vrho();
+    m.rho_n = c->d_rho_n();
     m.tau1 = c->tau1;
     if (timed) {
         if (c->ev_used + 2 > c->ev.size()) {
@@ -279,6 +279,18 @@ int enqueue_step(lbm_ctx *c, bool timed) {
         HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
+    LinkArgs la;
+    la.desc = c->d_desc();
+    la.state = c->d_state();
+    la.k3_begin = c->d_tables() + (c->nrep + 1);
+    la.nrep = c->nrep;
+    la.buf = c->d_pop(1 - c->cur);
+    la.pmask = c->d_pmask();
+    la.vrho = c->d_vrho();
+    la.rho_n = c->d_rho_n();
+    la.part1 = c->d_part1();
+    e = launch_links(c->prec, la, c->k3_grid, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "link kernel launch");
     ParticleArgs pa;
     pa.desc = c->d_desc();
     pa.state = c->d_state();
@@ -287,6 +299,8 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     pa.buf = c->d_pop(1 - c->cur);
     pa.part1 = c->d_part1();
     pa.part3 = c->d_part3();
+    pa.part3b = c->d_part3b();
+    pa.pmask = c->d_pmask();
     pa.raw = c->d_raw();
     pa.flags = c->d_flags();
     pa.vrho = c->d_vrho();
@@ -356,7 +370,6 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
         D.S = L.S[r];
         D.has_particle = has_sphere(q);
         D.bbox_off = L.bbox_off[r];
-        D.part1_off = L.part1_off[r];
         D.part3_off = L.part3_off[r];
         D.series_off = L.series_off[r];
         D.series_cap = q.series_cap;
@@ -400,6 +413,7 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
     ia.buf = c->d_pop(0);
     ia.mass = c->d_aux();
     ia.vrho = c->d_vrho();
+    ia.pmask = c->d_pmask();
     if (e == hipSuccess) e = launch_init(precision, ia, c->init_grid, n_replicas, c->stream);
     std::vector<double> mass(2 * L.init_tot);
     if (e == hipSuccess)
@@ -518,6 +532,7 @@ LBM_API int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f) {
         a.z_begin = z0;
         a.z_end = z1;
         a.src = c->d_pop(c->cur);
+        a.pmask = c->d_pmask();
         a.out = reinterpret_cast<double *>(c->d_pop(1 - c->cur));
         hipError_t e = launch_export(c->prec, a, cnt, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "export kernel launch");
@@ -540,6 +555,7 @@ int run_fields(lbm_ctx *c, int r, bool columns) {
     a.state = c->d_state();
     a.rep = r;
     a.src = c->d_pop(c->cur);
+    a.pmask = c->d_pmask();
     a.vrho = c->d_vrho();
     a.scratch = reinterpret_cast<double *>(c->d_pop(1 - c->cur));
     a.columns = columns ? c->d_aux() : nullptr;
@@ -624,7 +640,8 @@ LBM_API int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t c
 
 LBM_API int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    *bytes = 38 * c->L.Ntot * c->es + sizeof(RepState) * c->nrep + sizeof(double) * 2 * c->L.S3tot;
+    *bytes = 38 * c->L.Ntot * c->es + sizeof(RepState) * c->nrep +
+             (sizeof(double) * 2 + sizeof(uint32_t)) * c->L.S3tot;
     return LBM_OK;
 }
 
@@ -634,9 +651,12 @@ LBM_API int lbm_checkpoint(lbm_ctx *c, void *dev_dst) {
     const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
     HIP_TRY(c, hipMemcpyAsync(d, c->d_pop(c->cur), pb, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d + pb, c->d_state(), sb, hipMemcpyDeviceToDevice, c->stream));
-    if (c->L.S3tot)
+    if (c->L.S3tot) {
         HIP_TRY(c, hipMemcpyAsync(d + pb + sb, c->d_vrho(), sizeof(double) * 2 * c->L.S3tot,
                                   hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d + pb + sb + sizeof(double) * 2 * c->L.S3tot, c->d_pmask(),
+                                  sizeof(uint32_t) * c->L.S3tot, hipMemcpyDeviceToDevice, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -647,9 +667,12 @@ LBM_API int lbm_restore(lbm_ctx *c, const void *dev_src) {
     const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
     HIP_TRY(c, hipMemcpyAsync(c->d_pop(c->cur), d, pb, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_state(), d + pb, sb, hipMemcpyDeviceToDevice, c->stream));
-    if (c->L.S3tot)
+    if (c->L.S3tot) {
         HIP_TRY(c, hipMemcpyAsync(c->d_vrho(), d + pb + sb, sizeof(double) * 2 * c->L.S3tot,
                                   hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_pmask(), d + pb + sb + sizeof(double) * 2 * c->L.S3tot,
+                                  sizeof(uint32_t) * c->L.S3tot, hipMemcpyDeviceToDevice, c->stream));
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }

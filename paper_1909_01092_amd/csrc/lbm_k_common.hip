@@ -23,6 +23,7 @@ __global__ __launch_bounds__(256) void k_init_layer(InitArgs a) {
     for (int q = 0; q < 3; q++) org[q] = (int)floor(X[q] - D.radius) - 2;
     const int Sx = D.S, S3 = Sx * Sx * Sx;
     double *vrho = a.vrho + D.bbox_off * 2;
+    uint32_t *pmask = a.pmask + D.bbox_off;
     auto init_rho = [&](int x, int y, int z, int l) {
         uint32_t c0 = (uint32_t)nidx(x, y, z, g), c1 = 0u, c2 = 0u, c3 = 1u;
         philox4x32_10(c0, c1, c2, c3, D.key0, D.key1);
@@ -42,7 +43,9 @@ __global__ __launch_bounds__(256) void k_init_layer(InitArgs a) {
             }
             p[q] = v;
         }
-        if (!in || !pnode(p[0], p[1], p[2], X, D.R2, g)) continue;
+        const bool solid = in && pnode(p[0], p[1], p[2], X, D.R2, g);
+        pmask[b] = solid ? MASK_SOLID : 0u;  // populations of step 0 sit in own slots
+        if (!solid) continue;
         ns[0] += 1.0;
         double s0 = 0.0, s1 = 0.0;
         int cnt = 0;
@@ -125,6 +128,12 @@ hipError_t launch_main(int prec, const MainArgs &a, int grid, int block, size_t 
     if (prec == 0) return launch_main_f64(a, grid, block, lds, s);
     if (prec == 1) return launch_main_f32(a, grid, block, lds, s);
     return launch_main_f16(a, grid, block, lds, s);
+}
+
+hipError_t launch_links(int prec, const LinkArgs &a, int grid, hipStream_t s) {
+    if (prec == 0) return launch_links_f64(a, grid, s);
+    if (prec == 1) return launch_links_f32(a, grid, s);
+    return launch_links_f16(a, grid, s);
 }
 
 hipError_t launch_particle(int prec, const ParticleArgs &a, int grid, hipStream_t s) {

@@ -14,9 +14,22 @@ struct MainArgs {
     int32_t nrep;
     const void *src;           // populations of step n (post-collision of n-1)
     void *dst;                 // post-collision populations of step n
-    double *part1;             // per-workgroup link partials
-    const double *vrho;        // wetting-layer densities of step n
+    const uint32_t *pmask;     // node masks of step n (bbox)
+    const double *vrho;        // wetting-layer densities of step n (bbox)
+    double *rho_n;             // densities of step n near the sphere (bbox), written
     int32_t tau1;              // every relaxation time of every replica is 1
+};
+
+struct LinkArgs {
+    const RepDesc *desc;
+    const RepState *state;
+    const int32_t *k3_begin;
+    int32_t nrep;
+    void *buf;                 // post-collision populations of step n (pre-bounced here)
+    const uint32_t *pmask;
+    const double *vrho;
+    const double *rho_n;
+    double *part1;             // per-workgroup link partials
 };
 
 struct ParticleArgs {
@@ -24,9 +37,11 @@ struct ParticleArgs {
     RepState *state;
     const int32_t *k3_begin;
     int32_t nrep;
-    void *buf;                 // post-collision populations just written by k_main
-    const double *part1;
-    double *part3;
+    void *buf;                 // post-collision populations of step n
+    const double *part1;       // link partials
+    double *part3;             // covered-node partials
+    double *part3b;            // uncovered-node partials
+    uint32_t *pmask;           // node masks of step n+1, written
     double *raw;
     uint8_t *flags;
     double *vrho;
@@ -41,6 +56,7 @@ struct InitArgs {
     void *buf;
     double *mass;              // 2 per init workgroup
     double *vrho;
+    uint32_t *pmask;
 };
 
 struct ExportArgs {
@@ -49,6 +65,7 @@ struct ExportArgs {
     int32_t rep;
     int32_t z_begin, z_end;
     const void *src;
+    const uint32_t *pmask;
     double *out;
 };
 
@@ -57,6 +74,7 @@ struct FieldArgs {
     const RepState *state;
     int32_t rep;
     const void *src;
+    const uint32_t *pmask;
     const double *vrho;
     double *scratch;           // 9 N doubles
     double *columns;           // 8 nx ny doubles, or null
@@ -64,6 +82,7 @@ struct FieldArgs {
 
 // dispatch on the storage precision (0 FP64, 1 FP32, 2 FP16)
 hipError_t launch_main(int prec, const MainArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_links(int prec, const LinkArgs &a, int grid, hipStream_t s);
 hipError_t launch_particle(int prec, const ParticleArgs &a, int grid, hipStream_t s);
 hipError_t launch_init(int prec, const InitArgs &a, int grid, int nrep, hipStream_t s);
 hipError_t launch_export(int prec, const ExportArgs &a, int64_t count, hipStream_t s);
@@ -71,6 +90,7 @@ hipError_t launch_fields(int prec, const FieldArgs &a, int64_t N, int64_t plane,
 
 #define LBM_DECLARE(SUFFIX)                                                                        \
     hipError_t launch_main_##SUFFIX(const MainArgs &, int, int, size_t, hipStream_t);              \
+    hipError_t launch_links_##SUFFIX(const LinkArgs &, int, hipStream_t);                          \
     hipError_t launch_particle_##SUFFIX(const ParticleArgs &, int, hipStream_t);                   \
     hipError_t launch_init_##SUFFIX(const InitArgs &, int, hipStream_t);                           \
     hipError_t launch_export_##SUFFIX(const ExportArgs &, int64_t, hipStream_t);                   \

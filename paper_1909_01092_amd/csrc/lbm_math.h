@@ -16,20 +16,20 @@ constexpr int Q = 19;
 
 // D3Q19 velocities: rest, axis links in (+,-) pairs, planar diagonals in
 // opposite pairs (xy, xz, yz).
-__host__ __device__ constexpr int cx(int i) {
+__host__ __device__ __forceinline__ constexpr int cx(int i) {
     return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
          : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
 }
-__host__ __device__ constexpr int cy(int i) {
+__host__ __device__ __forceinline__ constexpr int cy(int i) {
     return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
          : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
 }
-__host__ __device__ constexpr int cz(int i) {
+__host__ __device__ __forceinline__ constexpr int cz(int i) {
     return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
          : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
 }
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr double wgt(int i) {
+__host__ __device__ __forceinline__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ __forceinline__ constexpr double wgt(int i) {
     return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
@@ -123,19 +123,19 @@ struct Coef {
 };
 
 // b_k = sum_i w_i e_k(c_i)^2 of the mode set used by modes_hi / back_transform
-__host__ __device__ constexpr double mode_norm(int k) {
+__host__ __device__ __forceinline__ constexpr double mode_norm(int k) {
     return k == 0 ? 1.0 : k <= 3 ? 1.0 / 3.0 : k == 4 ? 2.0 / 3.0 : k == 5 ? 4.0 / 3.0
          : k == 6 ? 4.0 / 9.0 : k <= 9 ? 1.0 / 9.0 : k <= 12 ? 2.0 / 3.0 : k <= 15 ? 2.0 / 9.0
          : k == 16 ? 2.0 : k == 17 ? 4.0 / 3.0 : 4.0 / 9.0;
 }
 // sqrt(b_k), 1 / b_k as literals
-__host__ __device__ constexpr double sqrt_norm(int k) {
+__host__ __device__ __forceinline__ constexpr double sqrt_norm(int k) {
     return k == 0 ? 1.0 : k <= 3 ? 0.57735026918962576 : k == 4 ? 0.81649658092772603
          : k == 5 ? 1.1547005383792515 : k == 6 ? 0.66666666666666667 : k <= 9 ? 0.33333333333333333
          : k <= 12 ? 0.81649658092772603 : k <= 15 ? 0.47140452079103169 : k == 16 ? 1.4142135623730951
          : k == 17 ? 1.1547005383792515 : 0.66666666666666667;
 }
-__host__ __device__ constexpr double inv_norm(int k) {
+__host__ __device__ __forceinline__ constexpr double inv_norm(int k) {
     return k == 0 ? 1.0 : k <= 3 ? 3.0 : k == 4 ? 1.5 : k == 5 ? 0.75 : k == 6 ? 2.25
          : k <= 9 ? 9.0 : k <= 12 ? 1.5 : k <= 15 ? 4.5 : k == 16 ? 0.5 : k == 17 ? 0.75 : 2.25;
 }

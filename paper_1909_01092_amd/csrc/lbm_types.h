@@ -24,8 +24,7 @@ struct RepDesc {
     int32_t S;               // edge of the particle bounding box (nodes)
     int32_t has_particle;
     int64_t bbox_off;        // element offset of this replica in the bbox arrays (S^3 each)
-    int64_t part1_off;       // double offset of main-kernel partials (16 per workgroup)
-    int64_t part3_off;       // double offset of particle-kernel partials (16 per workgroup)
+    int64_t part3_off;       // double offset of the link and particle partials (16 per workgroup)
     int64_t series_off;      // double offset of the U series ring (3 per entry)
     int32_t series_cap;
     int32_t cz;              // z-chunk of the main kernel
@@ -56,9 +55,21 @@ struct RepState {
     uint32_t flags;          // bit0 unstable
     uint32_t k3_done;        // particle-kernel completion counter
     uint32_t pad1[2];
+    // sphere update of the step in flight (written by the first particle kernel)
+    double Xn[3], Un[3], Wn[3], Fn[3], Tn[3];
+    double dMbb[2];          // bounce-back mass flux of the step
+    double nlinks;
+    int32_t orgn[3];
+    int32_t pad2;
 };
 
 constexpr uint32_t FLAG_UNSTABLE = 1u;
+// Node mask of a bounding-box node for one step: bit i (1..18) = the pull of
+// direction i bounces (x - c_i is a particle node at X^{n-1}); MASK_SOLID =
+// particle node at X^n; MASK_LOCAL = uncovered at this step (populations in
+// the node's own slots).
+constexpr uint32_t MASK_SOLID = 1u << 19;
+constexpr uint32_t MASK_LOCAL = 1u << 20;
 constexpr int PART = 16;     // doubles per workgroup partial
 
 }  // namespace lbm
