@@ -41,7 +41,7 @@ struct Layout {
         total;
     std::vector<int64_t> pop_off, bbox_off, part3_off, series_off, init_wg;
     std::vector<int> S, k3_count;
-    int64_t Ntot = 0, S3tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
+    int64_t Ntot = 0, NPtot = 0, S3tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
     size_t aux_doubles = 0;
 };
 
@@ -53,7 +53,9 @@ Layout plan(const lbm_params *p, int n, int prec) {
     size_t max_cols = 0;
     for (int r = 0; r < n; r++) {
         const int64_t N = (int64_t)p[r].nx * p[r].ny * p[r].nz;
-        L.pop_off[r] = 38 * L.Ntot;
+        const int64_t NP = (int64_t)(p[r].nx + 2) * (p[r].ny + 2) * (p[r].nz + 2);
+        L.pop_off[r] = 38 * L.NPtot;
+        L.NPtot += NP;
         L.Ntot += N;
         L.S[r] = bbox_edge(p[r]);
         const int64_t S3 = (int64_t)L.S[r] * L.S[r] * L.S[r];
@@ -74,8 +76,8 @@ Layout plan(const lbm_params *p, int n, int prec) {
     L.tables = take(sizeof(int32_t) * 3 * (n + 1));
     L.desc = take(sizeof(RepDesc) * n);
     L.state = take(sizeof(RepState) * n);
-    L.pop[0] = take(38 * L.Ntot * es);
-    L.pop[1] = take(38 * L.Ntot * es);
+    L.pop[0] = take(38 * L.NPtot * es);
+    L.pop[1] = take(38 * L.NPtot * es);
     L.part1 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
     L.part3 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
     L.part3b = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
@@ -108,7 +110,7 @@ std::string validate(const lbm_params *p, int n, int prec) {
         const int nn[3] = {q.nx, q.ny, q.nz};
         if (q.nx < 2 || q.ny < 2 || q.nz < 2) return fmt("replica %d: every axis needs >= 2 nodes", r);
         if (q.nx > MAIN_BLOCK_MIN) return fmt("replica %d: nx = %d exceeds %d", r, q.nx, MAIN_BLOCK_MIN);
-        if ((int64_t)q.nx * q.ny * q.nz >= (int64_t(1) << 31) / 38)
+        if ((int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2) >= (int64_t(1) << 31) / 38)
             return fmt("replica %d: lattice too large for one replica", r);
         if (q.walls > 7u) return fmt("replica %d: walls must be a 3-bit mask", r);
         if (!(q.rho0[0] > 0.0) || !(q.rho0[1] > 0.0)) return fmt("replica %d: rho0 must be > 0", r);
@@ -366,6 +368,7 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
         std::memset(&D, 0, sizeof(D));
         D.nx = q.nx; D.ny = q.ny; D.nz = q.nz; D.walls = q.walls;
         D.N = (int64_t)q.nx * q.ny * q.nz;
+        D.NP = (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
         D.pop_off = L.pop_off[r];
         D.S = L.S[r];
         D.has_particle = has_sphere(q);
@@ -398,7 +401,6 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
             s.U[a] = D.has_particle ? q.U0[a] : 0.0;
             s.W[a] = D.has_particle ? q.W0[a] : 0.0;
         }
-        s.local_read = 1;
     }
     build_tiling(c);
     int rc = upload_desc(c);
@@ -519,7 +521,7 @@ LBM_API int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f) {
     if (!host_f) return fail(c, LBM_EINVAL, "host_f is NULL");
     const lbm_params &q = c->p[replica];
     const int64_t plane = (int64_t)q.nx * q.ny, N = plane * q.nz;
-    const size_t cap = 38 * c->L.Ntot * c->es;  // the free population buffer is the scratch
+    const size_t cap = 38 * c->L.NPtot * c->es;  // the free population buffer is the scratch
     int zs = (int)std::max<int64_t>(1, std::min<int64_t>(q.nz, cap / (38 * plane * sizeof(double))));
     std::vector<double> host((size_t)38 * plane * zs);
     for (int z0 = 0; z0 < q.nz; z0 += zs) {
@@ -640,7 +642,7 @@ LBM_API int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t c
 
 LBM_API int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    *bytes = 38 * c->L.Ntot * c->es + sizeof(RepState) * c->nrep +
+    *bytes = 38 * c->L.NPtot * c->es + sizeof(RepState) * c->nrep +
              (sizeof(double) * 2 + sizeof(uint32_t)) * c->L.S3tot;
     return LBM_OK;
 }
@@ -648,7 +650,7 @@ LBM_API int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes) {
 LBM_API int lbm_checkpoint(lbm_ctx *c, void *dev_dst) {
     if (!c || !dev_dst) return LBM_EINVAL;
     char *d = reinterpret_cast<char *>(dev_dst);
-    const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
+    const size_t pb = 38 * c->L.NPtot * c->es, sb = sizeof(RepState) * c->nrep;
     HIP_TRY(c, hipMemcpyAsync(d, c->d_pop(c->cur), pb, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d + pb, c->d_state(), sb, hipMemcpyDeviceToDevice, c->stream));
     if (c->L.S3tot) {
@@ -664,7 +666,7 @@ LBM_API int lbm_checkpoint(lbm_ctx *c, void *dev_dst) {
 LBM_API int lbm_restore(lbm_ctx *c, const void *dev_src) {
     if (!c || !dev_src) return LBM_EINVAL;
     const char *d = reinterpret_cast<const char *>(dev_src);
-    const size_t pb = 38 * c->L.Ntot * c->es, sb = sizeof(RepState) * c->nrep;
+    const size_t pb = 38 * c->L.NPtot * c->es, sb = sizeof(RepState) * c->nrep;
     HIP_TRY(c, hipMemcpyAsync(c->d_pop(c->cur), d, pb, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_state(), d + pb, sb, hipMemcpyDeviceToDevice, c->stream));
     if (c->L.S3tot) {

@@ -9,8 +9,19 @@
 // leap-frog Newton, moving bounce-back with momentum exchange,
 // cover/uncover, mass correction, virtual wetting layer).  Sec. 3: eq. (fp).
 //
-// One step = k_main (all nodes of all replicas) + k_particle (bounding box
-// of each sphere; the last workgroup per replica finishes the step).
+// Storage.  Each replica keeps its populations on a lattice padded by one
+// ghost layer per side, [component][direction][z+1][y+1][x+1].  Node x pulls
+// population i of step n from the padded position x - c_i, slot i.  Whoever
+// produces a value that does not arrive by plain streaming writes it into
+// exactly that slot: a node next to a wall writes its bounced value into the
+// wall's ghost, a node next to a periodic face writes the wrapped copy into
+// the ghost, the link kernel writes the sphere's moving-wall bounce-back into
+// the particle node's slot, and uncovered nodes get f_eq written into the
+// slots they pull from.  Every pull is therefore 38 loads at wave-uniform
+// offsets from the node's own index.
+//
+// One step = k_main (all nodes of all replicas) + k_links + k_particle_a +
+// k_particle_b (bounding box of each sphere).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,7 +57,9 @@ __device__ __forceinline__ void st_dev(S *p, T v, T inv_scale) {
 struct Geo {
     int nx, ny, nz;
     bool wx, wy, wz;
-    int64_t N;
+    int64_t N;          // nodes
+    int PX, PY;         // padded row and plane widths (nx + 2, ny + 2)
+    uint32_t NP;        // padded nodes per component and direction
 };
 
 __device__ __forceinline__ Geo geo_of(const RepDesc &D) {
@@ -54,9 +67,20 @@ __device__ __forceinline__ Geo geo_of(const RepDesc &D) {
     g.nx = D.nx; g.ny = D.ny; g.nz = D.nz;
     g.wx = D.walls & 1u; g.wy = D.walls & 2u; g.wz = D.walls & 4u;
     g.N = D.N;
+    g.PX = D.nx + 2;
+    g.PY = D.ny + 2;
+    g.NP = (uint32_t)D.NP;
     return g;
 }
 
+// padded index of lattice position (x, y, z), -1 <= x <= nx etc.
+__device__ __forceinline__ uint32_t pidx(int x, int y, int z, const Geo &g) {
+    return (uint32_t)(x + 1) + (uint32_t)g.PX * ((uint32_t)(y + 1) + (uint32_t)g.PY * (uint32_t)(z + 1));
+}
+// unpadded node index (noise counter, fields)
+__device__ __forceinline__ uint32_t nidx(int x, int y, int z, const Geo &g) {
+    return (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+}
 // bring a coordinate one layer outside the box back in; false = wall layer
 __device__ __forceinline__ bool wrap1(int &v, int n, bool wall) {
     if (v < 0 || v >= n) {
@@ -65,6 +89,11 @@ __device__ __forceinline__ bool wrap1(int &v, int n, bool wall) {
     }
     return true;
 }
+// padded-index offset of direction i
+__device__ __forceinline__ int32_t doff(int i, const Geo &g) {
+    return cx(i) + g.PX * (cy(i) + g.PY * cz(i));
+}
+
 // wall layers mirror onto the adjacent node, periodic axes wrap
 __device__ __forceinline__ int mirror1(int v, int n, bool wall) {
     if (v < 0) return wall ? 0 : v + n;
@@ -96,43 +125,6 @@ __device__ __forceinline__ bool pnode(int x, int y, int z, const double *X, doub
     return d2 < R2;
 }
 
-// cheap conservative test: within lim of X along every axis
-__device__ __forceinline__ bool near_box(int x, int y, int z, const double *X, double lim,
-                                         const Geo &g) {
-    return fabs(sepd((double)x - X[0], g.nx, g.wx)) < lim &&
-           fabs(sepd((double)y - X[1], g.ny, g.wy)) < lim &&
-           fabs(sepd((double)z - X[2], g.nz, g.wz)) < lim;
-}
-
-// node index inside a replica (a replica block of 38 N elements fits 32 bits)
-__device__ __forceinline__ uint32_t nidx(int x, int y, int z, const Geo &g) {
-    return (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
-}
-
-// Integer box around the sphere centre X, widened by lim on every side, in
-// which exact particle predicates are evaluated.  Periodic axes test the
-// three images of a coordinate.
-struct NearBox {
-    int lo[3], hi[3];
-};
-__device__ __forceinline__ NearBox near_bounds(const double *X, double lim) {
-    NearBox b;
-    for (int a = 0; a < 3; a++) {
-        b.lo[a] = (int)floor(X[a] - lim);
-        b.hi[a] = (int)ceil(X[a] + lim);
-    }
-    return b;
-}
-__device__ __forceinline__ bool in_range(int v, int lo, int hi, int n, bool wall) {
-    if (v >= lo && v <= hi) return true;
-    if (wall) return false;
-    return (v + n >= lo && v + n <= hi) || (v - n >= lo && v - n <= hi);
-}
-__device__ __forceinline__ bool near_int(int x, int y, int z, const NearBox &b, const Geo &g) {
-    return in_range(x, b.lo[0], b.hi[0], g.nx, g.wx) && in_range(y, b.lo[1], b.hi[1], g.ny, g.wy) &&
-           in_range(z, b.lo[2], b.hi[2], g.nz, g.wz);
-}
-
 __device__ __forceinline__ int find_rep(const int32_t *begin, int nrep, int wg) {
     int lo = 0, hi = nrep - 1;
     while (lo < hi) {
@@ -154,69 +146,89 @@ __device__ __forceinline__ int bbox_index(int x, int y, int z, const int32_t *or
     return (bz * S + by) * S + bx;
 }
 
+// position of bbox entry b (origin org, edge S); false when it lies in a wall layer
+__device__ __forceinline__ bool bbox_pos(int b, const int32_t *org, int S, const Geo &g, int (&bb)[3],
+                                         int (&p)[3]) {
+    bb[0] = b % S; bb[1] = (b / S) % S; bb[2] = b / (S * S);
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    const bool w3[3] = {g.wx, g.wy, g.wz};
+    bool in = true;
+    for (int q = 0; q < 3; q++) {
+        int v = org[q] + bb[q];
+        if (v < 0 || v >= n3[q]) {
+            if (w3[q]) in = false;
+            else v = ((v % n3[q]) + n3[q]) % n3[q];
+        }
+        p[q] = v;
+    }
+    return in;
+}
+
 // ------------------------------------------------------------------ pulling
-// Populations f_{l i}(x, n) of a fluid node in deviation form: each comes from
-// the post-collision slot i of x - c_i, or - when x - c_i is a wall layer or a
-// particle node at X^{n-1} (bit i of the node mask) - from the node's own slot
-// opp(i), which the previous step stored already bounced.  Nodes uncovered
-// at this step (MASK_LOCAL), and every node right after initialisation, hold
-// their populations in their own slots.  The mass correction of the previous
-// step adds w_i delta_l.
+// Populations f_{l i}(x, n) of a fluid node in deviation form: slot i at the
+// padded position x - c_i (see the storage note at the top).
 template <typename S, typename T>
 struct PullCtx {
     const S *src;          // replica block
-    Geo g;
-    bool local_read;
-    T delta[2];
+    int32_t NP, PX, PXY;   // padded sizes
     T scale[2];            // FP16 relative storage: rho0_l (times w_i per slot)
 };
 
 template <typename S, typename T>
-__device__ __forceinline__ PullCtx<S, T> pull_ctx(const void *buf, const RepDesc &D,
-                                                  const RepState &st, bool with_delta) {
+__device__ __forceinline__ PullCtx<S, T> pull_ctx(const void *buf, const RepDesc &D, const Geo &g) {
     PullCtx<S, T> pc;
     pc.src = reinterpret_cast<const S *>(buf) + D.pop_off;
-    pc.g = geo_of(D);
-    pc.local_read = st.local_read != 0;
-    for (int l = 0; l < 2; l++) {
-        pc.delta[l] = with_delta ? T(st.delta[l]) : T(0);
-        pc.scale[l] = Rel<S>::value ? T(D.rho0[l]) : T(1);
-    }
+    pc.NP = (int32_t)g.NP;
+    pc.PX = g.PX;
+    pc.PXY = g.PX * g.PY;
+    for (int l = 0; l < 2; l++) pc.scale[l] = Rel<S>::value ? T(D.rho0[l]) : T(1);
     return pc;
 }
 
+// element at a wave-uniform base plus a per-lane byte offset (lets the
+// compiler use scalar-base + 32-bit vector-offset addressing)
+template <typename S>
+__device__ __forceinline__ const S &at(const S *base, uint32_t byte_off) {
+    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename S>
+__device__ __forceinline__ S &at(S *base, uint32_t byte_off) {
+    return *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
 template <typename S, typename T>
-__device__ __forceinline__ void pull_node(const PullCtx<S, T> &c, int x, int y, int z, uint32_t mask,
-                                          T (&d)[2][Q]) {
-    const uint32_t own = nidx(x, y, z, c.g);
-    const uint32_t N = (uint32_t)c.g.N;
-    const bool loc = c.local_read || (mask & MASK_LOCAL);
+__device__ __forceinline__ void pull_node(const PullCtx<S, T> &c, uint32_t own, T (&d)[2][Q]) {
+    const S *b0 = c.src, *b1 = c.src + Q * c.NP;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        uint32_t idx = own;
-        int slot = i;
-        if (!loc && i != 0) {
-            int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
-            bool ok = !((mask >> i) & 1u);
-            if (cx(i) != 0) ok = ok && wrap1(sx, c.g.nx, c.g.wx);
-            if (cy(i) != 0) ok = ok && wrap1(sy, c.g.ny, c.g.wy);
-            if (cz(i) != 0) ok = ok && wrap1(sz, c.g.nz, c.g.wz);
-            if (ok) idx = nidx(sx, sy, sz, c.g);
-            else slot = opp(i);
-        }
         const T w = T(wgt(i));
-#pragma unroll
-        for (int l = 0; l < 2; l++)
-            d[l][i] = ld_dev<S, T>(c.src + ((uint32_t)(l * Q + slot) * N + idx), w * c.scale[l]) +
-                      w * c.delta[l];
+        const int32_t off = cx(i) + c.PX * cy(i) + c.PXY * cz(i);
+        const uint32_t vo = (own + (uint32_t)(i * c.NP - off)) * (uint32_t)sizeof(S);
+        d[0][i] = ld_dev<S, T>(&at(b0, vo), w * c.scale[0]);
+        d[1][i] = ld_dev<S, T>(&at(b1, vo), w * c.scale[1]);
     }
 }
 
-// mask of a box node for the current step (0 outside the bounding box)
-__device__ __forceinline__ uint32_t node_mask(int x, int y, int z, const uint32_t *pmask,
-                                              const int32_t *org, int S, const Geo &g, int &b) {
-    b = bbox_index(x, y, z, org, S, g);
-    return b >= 0 ? pmask[b] : 0u;
+// Where the post-collision value f*_i of box node (x, y, z) must also be
+// written when its link leaves the box: into the wall ghost x + c_i, slot
+// opp(i) (half-way bounce-back), or, across periodic faces only, into the
+// ghost wrap(x + c_i) - c_i, slot i.  Returns false for links inside the box.
+__device__ __forceinline__ bool exit_slot(int i, int x, int y, int z, const Geo &g, uint32_t &pos,
+                                          int &slot) {
+    const int tx = x + cx(i), ty = y + cy(i), tz = z + cz(i);
+    const bool ox = tx < 0 || tx >= g.nx, oy = ty < 0 || ty >= g.ny, oz = tz < 0 || tz >= g.nz;
+    if (!(ox || oy || oz)) return false;
+    if ((ox && g.wx) || (oy && g.wy) || (oz && g.wz)) {
+        pos = pidx(tx, ty, tz, g);
+        slot = opp(i);
+    } else {
+        const int wx = ox ? (tx < 0 ? tx + g.nx : tx - g.nx) : tx;
+        const int wy = oy ? (ty < 0 ? ty + g.ny : ty - g.ny) : ty;
+        const int wz = oz ? (tz < 0 ? tz + g.nz : tz - g.nz) : tz;
+        pos = pidx(wx - cx(i), wy - cy(i), wz - cz(i), g);
+        slot = i;
+    }
+    return true;
 }
 
 // What a collision needs from the pulled populations of a node: density
@@ -283,22 +295,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red /* [B/64]
     __syncthreads();
 }
 
-// position of bbox entry b (origin org, edge S); false when it lies in a wall layer
-__device__ __forceinline__ bool bbox_pos(int b, const int32_t *org, int S, const Geo &g, int (&bb)[3],
-                                         int (&p)[3]) {
-    bb[0] = b % S; bb[1] = (b / S) % S; bb[2] = b / (S * S);
-    const int n3[3] = {g.nx, g.ny, g.nz};
-    const bool w3[3] = {g.wx, g.wy, g.wz};
-    bool in = true;
-    for (int q = 0; q < 3; q++) {
-        int v = org[q] + bb[q];
-        if (v < 0 || v >= n3[q]) {
-            if (w3[q]) in = false;
-            else v = ((v % n3[q]) + n3[q]) % n3[q];
-        }
-        p[q] = v;
-    }
-    return in;
+// Workgroups are dispatched to the 8 XCDs round-robin; give each XCD a
+// contiguous run of logical tiles so halo rows and planes shared by
+// neighbouring tiles are read through the same L2.
+__device__ __forceinline__ int xcd_logical(int b, int G) {
+    const int q = G >> 3, r = G & 7, xcd = b & 7, slot = b >> 3;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
 // ================================================================ k_main
@@ -307,63 +309,74 @@ __device__ __forceinline__ bool bbox_pos(int b, const int32_t *org, int S, const
 // y0+rows, planes z-1 and z+1) sit in a 3-plane LDS ring; halo densities are
 // recomputed from pulled populations, so no density field goes through HBM.
 // The density and momenta of the next plane stay in registers while the
-// current plane collides.  The sphere enters only through the integer node
-// masks and the wetting-layer densities of its bounding box; every FP64
-// particle computation lives in k_links / k_particle.
+// current plane collides.  The sphere enters only through the solid flags
+// and wetting-layer densities of its bounding box; every FP64 particle
+// computation lives in the bounding-box kernels.
 template <typename S, typename T, int B, bool TAU1>
 __global__ __launch_bounds__(B) void k_main(MainArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *lds = reinterpret_cast<T *>(smem);
 
-    const int wg = blockIdx.x;
+    const int wg = xcd_logical(blockIdx.x, gridDim.x);
     const int r = find_rep(a.wg_begin, a.nrep, wg);
     const RepDesc &D = a.desc[r];
     RepState *stp = a.state + r;
     const Geo g = geo_of(D);
-    const int nx = g.nx;
+    const int nx = g.nx, ty = D.ty, zc = D.cz;
     const int local = wg - D.wg_begin;
     const int yt = local % D.nty, ch = local / D.nty;
-    const int y0 = yt * D.ty, rows = min(D.ty, g.ny - y0);
-    const int z0 = ch * D.cz, z1 = min(z0 + D.cz, g.nz);
+    const int y0 = yt * ty, rows = min(ty, g.ny - y0);
+    const int z0 = ch * zc, z1 = min(z0 + zc, g.nz);
     const int t = threadIdx.x;
     const int nin = nx * rows;
     const bool inner = t < nin;
     const int x = inner ? t % nx : 0, yl = inner ? t / nx : 0;
     const int y = y0 + yl;
-    const int pr = (D.ty + 2) * nx;  // LDS elements per plane and component
+    const int pr = (ty + 2) * nx;  // LDS elements per plane and component
 
     const bool hp = D.has_particle;
-    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, *stp, true);
-    const double dl[2] = {stp->delta[0], stp->delta[1]};
+    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
+    const T dl[2] = {T(stp->delta[0]), T(stp->delta[1])};
+    const double dld[2] = {stp->delta[0], stp->delta[1]};
     const uint32_t step = (uint32_t)stp->step;
     const int32_t org[3] = {stp->org[0], stp->org[1], stp->org[2]};
     const int Sx = D.S, S3 = Sx * Sx * Sx;
-    const uint32_t *pmask = a.pmask + D.bbox_off;
-    const double *vrho = a.vrho + D.bbox_off * 2;
-    double *rho_n = a.rho_n + D.bbox_off * 2;
-    S *dst = reinterpret_cast<S *>(a.dst) + D.pop_off;
-    const uint32_t N32 = (uint32_t)g.N;
+    const uint32_t *__restrict__ pmask = a.pmask + D.bbox_off;
+    const double *__restrict__ vrho = a.vrho + D.bbox_off * 2;
+    double *__restrict__ rho_n = a.rho_n + D.bbox_off * 2;
+    S *__restrict__ dst = reinterpret_cast<S *>(a.dst) + D.pop_off;
+    const uint32_t NP = g.NP;
+    const double rho0d[2] = {D.rho0[0], D.rho0[1]};
+    const T G = T(D.G);
+    const T af[3] = {T(D.af[0]), T(D.af[1]), T(D.af[2])};
+    const uint32_t key0 = D.key0, key1 = D.key1;
+    const Coef<T> cf = make_coef_dev<T>(D);
+    uint32_t k0 = key0, k1 = key1;
+    PullCtx<S, T> pcl = pc;
 
     auto L = [&](int zp, int l, int row, int xx) -> T & {
         const int slot = ((zp % 3) + 3) % 3;
         return lds[(slot * 2 + l) * pr + (row + 1) * nx + xx];
     };
 
-    // density deviation of a box node: pulled, or the wetting-layer value on
-    // particle nodes; fluid nodes also return their moments
+    // density deviation of a box node: pulled (plus the mass correction), or
+    // the wetting-layer value on particle nodes; fluid nodes also return
+    // their moments
     auto node_density = [&](int xx, int yy, int zz, NodeM<T, TAU1> &s, T &rA, T &rB) -> bool {
         int b = -1;
-        const uint32_t m = hp ? node_mask(xx, yy, zz, pmask, org, Sx, g, b) : 0u;
-        if (!(m & MASK_SOLID)) {
+        if (hp) b = bbox_index(xx, yy, zz, org, Sx, g);
+        if (b < 0 || !(pmask[b] & MASK_SOLID)) {
             T d[2][Q];
-            pull_node(pc, xx, yy, zz, m, d);
+            pull_node(pcl, pidx(xx, yy, zz, g), d);
             node_moments(d, s);
+            s.rd[0] += dl[0];
+            s.rd[1] += dl[1];
             rA = s.rd[0];
             rB = s.rd[1];
             return true;
         }
-        rA = T(vrho[b] + dl[0] - D.rho0[0]);
-        rB = T(vrho[S3 + b] + dl[1] - D.rho0[1]);
+        rA = T(vrho[b] + dld[0] - rho0d[0]);
+        rB = T(vrho[S3 + b] + dld[1] - rho0d[1]);
         return false;
     };
 
@@ -392,21 +405,22 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
         }
     };
 
-    const T G = T(D.G);
-    const Coef<T> cf = make_coef_dev<T>(D);
     const int xm = mirror1(x - 1, nx, g.wx), xp = mirror1(x + 1, nx, g.wx);
+    const bool xedge = x == 0 || x == nx - 1, yedge = y == 0 || y == g.ny - 1;
 
     // plane zp is filled while plane zp - 1 collides
     for (int zp = z0 - 1; zp <= z1; zp++) {
+        // keep uniform values derived from these roots inside the loop (scalar
+        // recomputation is cheaper than spilling hoisted copies)
+        asm volatile("" : "+s"(k0), "+s"(k1), "+s"(pcl.NP), "+s"(pcl.PX), "+s"(pcl.PXY));
         const NodeM<T, TAU1> cur = nxt;
         const bool cur_fluid = nxt_fluid;
         fill(zp);
         __syncthreads();
         if (zp <= z0) continue;
         const int z = zp - 1;
-        const bool active = inner && cur_fluid;
-        if (active) {
-            const uint32_t own = nidx(x, y, z, g);
+        if (inner && cur_fluid) {
+            const uint32_t own = pidx(x, y, z, g);
             const T(&rd)[2] = cur.rd;
             const T(&j)[2][3] = cur.j;
             // Shan-Chen: F_l = -G rho_l sum_i w_i rho~_l'(x + c_i) c_i + rho_l a_f
@@ -435,33 +449,61 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
             T F[2][3];
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                F[0][q] = -G * rl[0] * grad[1][q] + rl[0] * T(D.af[q]);
-                F[1][q] = -G * rl[1] * grad[0][q] + rl[1] * T(D.af[q]);
+                F[0][q] = -G * rl[0] * grad[1][q] + rl[0] * af[q];
+                F[1][q] = -G * rl[1] * grad[0][q] + rl[1] * af[q];
             }
+            const uint32_t node = (uint32_t)(x + nx * (y + g.ny * z));
             T u[3], xid[3];
             T zz[36];
-            if (cf.noise) noise_block<T>(own, step, 8u, D.key0, D.key1, zz + 32);
+            if (cf.noise) noise_block<T>(node, step, 8u, k0, k1, zz + 32);
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
-#pragma unroll
+            const bool edge = xedge || yedge || z == 0 || z == g.nz - 1;
+#pragma unroll 1
             for (int l = 0; l < 2; l++) {
+                // this component's values (selected, so nothing is indexed by l)
+                const T rdl = l ? rd[1] : rd[0];
+                const T jl[3] = {l ? j[1][0] : j[0][0], l ? j[1][1] : j[0][1], l ? j[1][2] : j[0][2]};
+                const T Fl[3] = {l ? F[1][0] : F[0][0], l ? F[1][1] : F[0][1], l ? F[1][2] : F[0][2]};
+                const T r0l = l ? cf.rho0[1] : cf.rho0[0];
+                const T sig = l ? T(-1) : T(1);
+                T zl[16];
                 if (cf.noise) {
 #pragma unroll
                     for (int b = 0; b < 4; b++)
-                        noise_block<T>(own, step, (uint32_t)(4 * l + b), D.key0, D.key1,
-                                       zz + 16 * l + 4 * b);
+                        noise_block<T>(node, step, (uint32_t)(4 * l + b), k0, k1, zl + 4 * b);
                 } else {
 #pragma unroll
-                    for (int k = 0; k < 16; k++) zz[16 * l + k] = T(0);
+                    for (int k = 0; k < 16; k++) zl[k] = T(0);
                 }
                 T out[Q];
-                if constexpr (TAU1) relax_tau1(l, rd[l], j[l], F[l], u, xid, zz, cf, out);
-                else relax_component(l, rd[l], j[l], cur.m[l], F[l], u, xid, zz, cf, out);
-                const T sc = Rel<S>::value ? cf.rho0[l] : T(1);
+                if constexpr (TAU1) {
+                    relax_tau1(r0l, sig, rdl, jl, Fl, u, xid, zl, cf, out);
+                } else {
+                    T ml[Q];
 #pragma unroll
-                for (int i = 0; i < Q; i++)
-                    st_dev<S, T>(dst + ((uint32_t)(l * Q + i) * N32 + own), out[i],
-                                 Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1));
+                    for (int k = 4; k < Q; k++) ml[k] = l ? cur.m[1][k] : cur.m[0][k];
+                    relax_component(r0l, sig, rdl, jl, ml, Fl, u, xid, zl, cf, out);
+                }
+                const T sc = Rel<S>::value ? r0l : T(1);
+                S *dl_base = dst + l * Q * (int32_t)NP;
+#pragma unroll
+                for (int i = 0; i < Q; i++) {
+                    const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
+                    st_dev<S, T>(&at(dl_base + i * (int32_t)NP, own * (uint32_t)sizeof(S)), out[i], inv);
+                }
+            }
+            // links that leave the box: copy the stored value into the ghost
+            // slot its receiver pulls from (bounce-back or periodic image)
+            if (edge) {
+#pragma unroll 1
+                for (int i = 1; i < Q; i++) {
+                    uint32_t pos;
+                    int slot;
+                    if (!exit_slot(i, x, y, z, g, pos, slot)) continue;
+                    for (int l = 0; l < 2; l++)
+                        dst[(uint32_t)(l * Q + slot) * NP + pos] = dst[(uint32_t)(l * Q + i) * NP + own];
+                }
             }
         }
         __syncthreads();
@@ -471,10 +513,10 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
 // =============================================================== k_links
 // Links from fluid nodes into the sphere at X^n (one thread per bbox entry):
 // moving-wall bounce-back f_opp(i)(x) = f*_i(x) - 6 w_i rho_l(x) (c_i . u_b)
-// written over the stored slot i, momentum exchange
-// sum_l (2 f*_i - 6 w_i rho_l c_i . u_b) c_i with its torque about X^n, the
-// bounce-back mass flux, and the reaction of the wetting layer on the
-// sphere.  Per-workgroup FP64 sums, fixed order.
+// written into the particle node's slot opp(i) at x + c_i (where x pulls it
+// from), momentum exchange sum_l (2 f*_i - 6 w_i rho_l c_i . u_b) c_i with
+// its torque about X^n, the bounce-back mass flux, and the reaction of the
+// wetting layer on the sphere.  Per-workgroup FP64 sums, fixed order.
 template <typename S, typename T, int B>
 __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
     __shared__ double red[(B / 64) * 16];
@@ -491,20 +533,19 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
     const double *vrho = a.vrho + D.bbox_off * 2;
     const double *rho_n = a.rho_n + D.bbox_off * 2;
     S *buf = reinterpret_cast<S *>(a.buf) + D.pop_off;
-    const uint32_t N32 = (uint32_t)g.N;
+    const uint32_t NP = g.NP;
     double acc[15];
     for (int k = 0; k < 15; k++) acc[k] = 0.0;
     const int b = local * B + t;
     if (b < S3) {
         int bb[3], p[3];
         const bool in = bbox_pos(b, org, Sx, g, bb, p);
-        const uint32_t m = pmask[b];
-        if (in && !(m & MASK_SOLID)) {
+        if (in && !(pmask[b] & MASK_SOLID)) {
             const double X[3] = {st.X[0], st.X[1], st.X[2]};
             const double U[3] = {st.U[0], st.U[1], st.U[2]};
             const double W[3] = {st.W[0], st.W[1], st.W[2]};
             const double rA = rho_n[b], rB = rho_n[S3 + b];
-            const uint32_t own = nidx(p[0], p[1], p[2], g);
+            const uint32_t own = pidx(p[0], p[1], p[2], g);
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
@@ -519,16 +560,20 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
                                       U[2] + W[0] * rr[1] - W[1] * rr[0]};
                 const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
                 const double rl[2] = {rA, rB};
+                // padded position x + c_i (a ghost when the link crosses a periodic face)
+                const uint32_t tgt = own + (uint32_t)doff(i, g);
                 double mom = 0.0;
 #pragma unroll
                 for (int l = 0; l < 2; l++) {
-                    S *ptr = buf + ((uint32_t)(l * Q + i) * N32 + own);
                     const double wr = wgt(i) * D.rho0[l];
-                    const double fs = wr + (double)ld_dev<S, T>(ptr, Rel<S>::value ? T(wr) : T(1));
+                    const T sc = Rel<S>::value ? T(wr) : T(1);
+                    const double fs =
+                        wr + (double)ld_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + own), sc);
                     const double corr = 6.0 * wgt(i) * rl[l] * cu;
                     mom += 2.0 * fs - corr;
                     acc[6 + l] -= corr;
-                    st_dev<S, T>(ptr, T(fs - corr - wr), Rel<S>::value ? T(1.0 / wr) : T(1));
+                    st_dev<S, T>(buf + ((uint32_t)(l * Q + opp(i)) * NP + tgt), T(fs - corr - wr),
+                                 Rel<S>::value ? T(1.0 / wr) : T(1));
                 }
                 const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
                 acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
@@ -559,9 +604,9 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
 // workgroup redundantly reduces the link partials (fixed order) and advances
 // the sphere (leap-frog Newton-Euler under F = links - wetting reaction +
 // F_ext + pending event momentum); workgroup 0 records the update.  Each
-// thread then builds its node's mask for step n+1 and, for nodes fluid at
-// X^n, pulls the step-(n+1) populations: densities for the wetting layer and
-// uncovered nodes, momentum and mass of nodes the sphere covers.
+// thread then flags its node for step n+1 and, for nodes fluid at X^n, pulls
+// the step-(n+1) populations: densities for the wetting layer and uncovered
+// nodes, momentum and mass of the nodes the sphere covers.
 template <typename S, typename T, int B>
 __global__ __launch_bounds__(B) void k_particle_a(ParticleArgs a) {
     __shared__ double red[(B / 64) * 16];
@@ -626,10 +671,9 @@ __global__ __launch_bounds__(B) void k_particle_a(ParticleArgs a) {
     double *raw = a.raw + D.bbox_off * 2;
     uint8_t *flags = a.flags + D.bbox_off;
     uint32_t *pmask = a.pmask + D.bbox_off;
-    PullCtx<S, T> pc = pull_ctx<S, T>(a.buf, D, *st, false);
-    pc.local_read = false;
+    const PullCtx<S, T> pc = pull_ctx<S, T>(a.buf, D, g);
 
-    // 4. node masks of step n+1; covered nodes (fluid at X^n, particle at
+    // 4. solid flags of step n+1; covered nodes (fluid at X^n, particle at
     // X^{n+1}) with the momentum of their step-(n+1) populations
     double cov[10];
     for (int k = 0; k < 10; k++) cov[k] = 0.0;
@@ -639,22 +683,10 @@ __global__ __launch_bounds__(B) void k_particle_a(ParticleArgs a) {
         const bool in = bbox_pos(b, org, Sx, g, bb, p);
         const bool fo = in && !pnode(p[0], p[1], p[2], X, D.R2, g);
         const bool fn = in && !pnode(p[0], p[1], p[2], Xn, D.R2, g);
-        uint32_t m = 0u;
-        if (in) {
-            if (!fn) m |= MASK_SOLID;
-            if (!fo && fn) m |= MASK_LOCAL;
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                int sx = p[0] - cx(i), sy = p[1] - cy(i), sz = p[2] - cz(i);
-                if (!(wrap1(sx, g.nx, g.wx) && wrap1(sy, g.ny, g.wy) && wrap1(sz, g.nz, g.wz)))
-                    continue;
-                if (pnode(sx, sy, sz, X, D.R2, g)) m |= 1u << i;
-            }
-        }
-        pmask[b] = m;
+        pmask[b] = (in && !fn) ? MASK_SOLID : 0u;
         if (fo) {
             T d[2][Q];
-            pull_node(pc, p[0], p[1], p[2], m & ~(MASK_SOLID | MASK_LOCAL), d);
+            pull_node(pc, pidx(p[0], p[1], p[2], g), d);
             double jt[3] = {0.0, 0.0, 0.0}, rho[2];
             for (int l = 0; l < 2; l++) {
                 T rd, jl[3], mm[Q];
@@ -709,12 +741,12 @@ __device__ __forceinline__ void mean_kept_neighbours(const int (&bb)[3], int Sx,
 
 // =========================================================== k_particle_b
 // One thread per node of the new bounding box.  Uncovered nodes (particle at
-// X^n, fluid at X^{n+1}) get f_eq(rho_bar, u_b) in their own slots, rho_bar
-// being the mean density of their neighbours fluid at both times; particle
-// nodes at X^{n+1} get the wetting-layer density: mean of their fluid
-// neighbours + / - Delta rho (the mass correction delta is added where it is
-// read).  The last workgroup sums the event partials, computes the global
-// mass correction and publishes the state of step n+1.
+// X^n, fluid at X^{n+1}) get f_eq(rho_bar, u_b) written into the slots they
+// pull from, rho_bar being the mean density of their neighbours fluid at
+// both times; particle nodes at X^{n+1} get the wetting-layer density: mean
+// of their fluid neighbours + / - Delta rho (the mass correction delta is
+// added where it is read).  The last workgroup sums the event partials,
+// computes the global mass correction and publishes the state of step n+1.
 template <typename S, typename T, int B>
 __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
     __shared__ double red[(B / 64) * 20];
@@ -734,7 +766,6 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
             double *s = series + 3 * (n % D.series_cap);
             s[0] = s[1] = s[2] = 0.0;
             st->delta[0] = st->delta[1] = 0.0;
-            st->local_read = 0;
             st->step = n + 1;
         }
         return;
@@ -748,7 +779,7 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
     double *vrho = a.vrho + D.bbox_off * 2;
     const uint8_t *flags = a.flags + D.bbox_off;
     S *buf = reinterpret_cast<S *>(a.buf) + D.pop_off;
-    const uint32_t N32 = (uint32_t)g.N;
+    const uint32_t NP = g.NP;
 
     double unc[10];
     for (int k = 0; k < 10; k++) unc[k] = 0.0;
@@ -766,14 +797,15 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
                                  Un[1] + Wn[2] * rr[0] - Wn[0] * rr[2],
                                  Un[2] + Wn[0] * rr[1] - Wn[1] * rr[0]};
             const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            const uint32_t own = nidx(p[0], p[1], p[2], g);
+            const uint32_t own = pidx(p[0], p[1], p[2], g);
             for (int i = 0; i < Q; i++) {
                 const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
                 const double e = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+                const uint32_t src = own - (uint32_t)doff(i, g);
                 for (int l = 0; l < 2; l++) {
                     const double wr = wgt(i) * D.rho0[l];
                     const double dev = wgt(i) * rb[l] * e - wr;
-                    st_dev<S, T>(buf + ((uint32_t)(l * Q + i) * N32 + own), T(dev),
+                    st_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + src), T(dev),
                                  Rel<S>::value ? T(1.0 / wr) : T(1));
                 }
             }
@@ -847,8 +879,7 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
     const int n3[3] = {g.nx, g.ny, g.nz};
     const bool w3[3] = {g.wx, g.wy, g.wz};
     bool bad = false;
-    for (int l = 0; l < 2; l++)
-        st->delta[l] = -(st->dMbb[l] - tot[6 + l] + utot[6 + l]) / nf;
+    for (int l = 0; l < 2; l++) st->delta[l] = -(st->dMbb[l] - tot[6 + l] + utot[6 + l]) / nf;
     for (int q = 0; q < 3; q++) {
         st->Xp[q] = st->X[q];
         st->X[q] = Xn[q];
@@ -867,7 +898,6 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
     st->n_cov += (int64_t)tot[9];
     st->n_unc += (int64_t)utot[9];
     st->n_links = (int64_t)st->nlinks;
-    st->local_read = 0;
     if (bad) st->flags |= FLAG_UNSTABLE;
     st->k3_done = 0;
     st->step = n + 1;
@@ -876,7 +906,7 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
 
 // ================================================================ k_init
 // f(0) = w_i rho_l(x) with rho_l = rho0_l + amp (2u - 1), u from Philox with
-// counter (node, 0, 0, 1), word l; written to the node's own slots.
+// counter (node, 0, 0, 1), word l, written into the slots x pulls from.
 template <typename S>
 __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     __shared__ double red[4 * 2];
@@ -895,14 +925,15 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
         philox4x32_10(c0, c1, c2, c3, D.key0, D.key1);
         const uint32_t w[2] = {c0, c1};
         S *dst = reinterpret_cast<S *>(a.buf) + D.pop_off;
+        const uint32_t own = pidx(x, y, z, g);
         for (int l = 0; l < 2; l++) {
             const double rho = D.rho0[l] + D.init_amp * (2.0 * (((double)w[l] + 0.5) * 0x1p-32) - 1.0);
-            if (!solid) m[l] = rho;
+            if (solid) continue;
+            m[l] = rho;
             for (int i = 0; i < Q; i++) {
                 const double wr = wgt(i) * D.rho0[l];
-                const double dev = solid ? 0.0 : wgt(i) * rho - wr;
-                st_dev<S, double>(dst + (int64_t)(l * Q + i) * g.N + n, dev,
-                                  Rel<S>::value ? 1.0 / wr : 1.0);
+                st_dev<S, double>(dst + ((uint32_t)(l * Q + i) * g.NP + own - (uint32_t)doff(i, g)),
+                                  wgt(i) * rho - wr, Rel<S>::value ? 1.0 / wr : 1.0);
             }
         }
     }
@@ -911,6 +942,13 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
         a.mass[2 * wg] = m[0];
         a.mass[2 * wg + 1] = m[1];
     }
+}
+
+// solid flag of a box node for the current step
+__device__ __forceinline__ bool solid_now(int x, int y, int z, const RepDesc &D, const RepState &st,
+                                          const uint32_t *pmask, const Geo &g, int &b) {
+    b = D.has_particle ? bbox_index(x, y, z, st.org, D.S, g) : -1;
+    return b >= 0 && (pmask[D.bbox_off + b] & MASK_SOLID);
 }
 
 // ============================================================= k_export
@@ -926,15 +964,15 @@ __global__ __launch_bounds__(256) void k_export(ExportArgs a) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= cnt) return;
     const int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = a.z_begin + (int)(k / plane);
-    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, st, true);
-    int b = -1;
-    const uint32_t m = D.has_particle ? node_mask(x, y, z, a.pmask + D.bbox_off, st.org, D.S, g, b) : 0u;
-    const bool solid = m & MASK_SOLID;
+    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
+    int b;
+    const bool solid = solid_now(x, y, z, D, st, a.pmask, g, b);
     T d[2][Q];
-    if (!solid) pull_node(pc, x, y, z, m, d);
+    if (!solid) pull_node(pc, pidx(x, y, z, g), d);
     for (int l = 0; l < 2; l++)
         for (int i = 0; i < Q; i++)
-            a.out[(int64_t)(l * Q + i) * cnt + k] = solid ? 0.0 : wgt(i) * D.rho0[l] + (double)d[l][i];
+            a.out[(int64_t)(l * Q + i) * cnt + k] =
+                solid ? 0.0 : wgt(i) * (D.rho0[l] + st.delta[l]) + (double)d[l][i];
 }
 
 // ============================================================= k_fields_a
@@ -950,9 +988,8 @@ __global__ __launch_bounds__(256) void k_fields_a(FieldArgs a) {
     const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny);
     const int z = (int)(n / ((int64_t)g.nx * g.ny));
     double *rt = a.scratch, *jt = a.scratch + 2 * g.N, *sol = a.scratch + 8 * g.N;
-    int b = -1;
-    const uint32_t m = D.has_particle ? node_mask(x, y, z, a.pmask + D.bbox_off, st.org, D.S, g, b) : 0u;
-    if (m & MASK_SOLID) {
+    int b;
+    if (solid_now(x, y, z, D, st, a.pmask, g, b)) {
         const int S3 = D.S * D.S * D.S;
         const double *vrho = a.vrho + D.bbox_off * 2;
         rt[n] = vrho[b] + st.delta[0];
@@ -961,14 +998,14 @@ __global__ __launch_bounds__(256) void k_fields_a(FieldArgs a) {
         sol[n] = 1.0;
         return;
     }
-    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, st, true);
+    const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
     T d[2][Q];
-    pull_node(pc, x, y, z, m, d);
+    pull_node(pc, pidx(x, y, z, g), d);
     double jtot[3] = {0.0, 0.0, 0.0};
     for (int l = 0; l < 2; l++) {
         T rd, jl[3], mm[Q];
         component_modes(d[l], rd, jl, mm);
-        rt[l * g.N + n] = D.rho0[l] + (double)rd;
+        rt[l * g.N + n] = D.rho0[l] + st.delta[l] + (double)rd;
         for (int q = 0; q < 3; q++) jtot[q] += (double)jl[q];
     }
     for (int q = 0; q < 3; q++) jt[q * g.N + n] = jtot[q];

@@ -73,10 +73,12 @@ __host__ __device__ inline void box_muller(uint32_t w1, uint32_t w2, float &z0, 
     const float t = big ? 1.0f - v : v;
 #if defined(__HIP_DEVICE_COMPILE__)
     const float L = __builtin_amdgcn_logf(t) * 0.69314718055994531f;
+    const float ratio = -v * __builtin_amdgcn_rcpf(t - 1.0f);
 #else
     const float L = logf(t);
+    const float ratio = -v / (t - 1.0f);
 #endif
-    const float lnu = big ? ((t == 1.0f) ? -v : L * (-v / (t - 1.0f))) : L;
+    const float lnu = big ? ((t == 1.0f) ? -v : L * ratio) : L;
     const float u2 = ((float)w2 + 0.5f) * 0x1p-32f;
 #if defined(__HIP_DEVICE_COMPILE__)
     const float r = __builtin_amdgcn_sqrtf(-2.0f * lnu);
@@ -164,6 +166,16 @@ __host__ __device__ inline Coef<T> make_coef(double rho0A, double rho0B, double 
 template <typename T>
 __host__ __device__ inline T tmax0(T a) { return a > T(0) ? a : T(0); }
 
+// 1/a: exact division in FP64, the hardware reciprocal (about 1 ulp) in FP32
+__host__ __device__ inline double recip(double a) { return 1.0 / a; }
+__host__ __device__ inline float recip(float a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(a);
+#else
+    return 1.0f / a;
+#endif
+}
+
 // Density deviation, momentum and modes 4..18 of one component (orthogonal
 // polynomial basis; modes of the deviation from w_i rho0 equal those of f for
 // k >= 1).
@@ -238,27 +250,26 @@ __host__ __device__ inline void common_velocity(const T (&rd)[2], const T (&j)[2
                                                 const T (&F)[2][3], const T (&z)[36],
                                                 const Coef<T> &c, T (&u)[3], T (&xid)[3]) {
     const T rA = c.rho0[0] + rd[0], rB = c.rho0[1] + rd[1];
-    const T inv = T(1) / (rA + rB);
+    const T inv = recip(rA + rB);
     for (int a = 0; a < 3; a++) u[a] = (j[0][a] + j[1][a] + T(0.5) * (F[0][a] + F[1][a])) * inv;
     const T amp = (c.noise && c.diffusive) ? c.ampd * sqrt(tmax0(rA) * tmax0(rB) * inv) : T(0);
     for (int a = 0; a < 3; a++) xid[a] = amp * z[32 + a];
 }
 
-// Post-collision deviations of component l (sigma = +1 for A, -1 for B):
+// Post-collision deviations of one component (sigma = +1 for A, -1 for B;
+// zl = its normals 0..14 for modes 4..18):
 //   j*  = rho_l u + g_j (j_l + F_l/2 - rho_l u) + F_l/2 + sigma xi_d
 //   m*_k = m_eq + g_k (m_k - m_eq) + (1 + g_k)/2 Phi_k + noise,   k = 4..9
 //   m*_k = g_g m_k + noise,                                         k = 10..18
 // noise amplitude sqrt(mu rho_l b_k (1 - g_k^2)), mu = kT / c_s^2.
 template <typename T>
-__host__ __device__ inline void relax_component(int l, T rd, const T (&j)[3], const T (&m)[Q],
-                                                const T (&Fl)[3], const T (&u)[3],
-                                                const T (&xid)[3], const T (&z)[36],
+__host__ __device__ inline void relax_component(T rho0l, T sig, T rd, const T (&j)[3],
+                                                const T (&m)[Q], const T (&Fl)[3], const T (&u)[3],
+                                                const T (&xid)[3], const T (&zl)[16],
                                                 const Coef<T> &c, T (&out)[Q]) {
-    const T r = c.rho0[l] + rd;
-    const T sig = l == 0 ? T(1) : T(-1);
+    const T r = rho0l + rd;
     const T sq = c.noise ? sqrt(tmax0(r)) : T(0);
     const T nb = c.nb * sq, ns = c.ns * sq, ng = c.ng * sq;
-    const T *zl = z + 16 * l;
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     T a[Q];
     a[0] = rd;
@@ -289,14 +300,12 @@ __host__ __device__ inline void relax_component(int l, T rd, const T (&j)[3], co
 // relax_component for gamma_k = 0 on every mode (all relaxation times 1): the
 // post-collision state depends on density and momentum only.
 template <typename T>
-__host__ __device__ inline void relax_tau1(int l, T rd, const T (&j)[3], const T (&Fl)[3],
-                                           const T (&u)[3], const T (&xid)[3], const T (&z)[36],
+__host__ __device__ inline void relax_tau1(T rho0l, T sig, T rd, const T (&j)[3], const T (&Fl)[3],
+                                           const T (&u)[3], const T (&xid)[3], const T (&zl)[16],
                                            const Coef<T> &c, T (&out)[Q]) {
-    const T r = c.rho0[l] + rd;
-    const T sig = l == 0 ? T(1) : T(-1);
+    const T r = rho0l + rd;
     const T sq = c.noise ? sqrt(tmax0(r)) : T(0);
     const T nb = c.nb * sq, ns = c.ns * sq, ng = c.ng * sq;
-    const T *zl = z + 16 * l;
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     T a[Q];
     a[0] = rd;
@@ -326,7 +335,12 @@ __host__ __device__ inline void collide(const T (&d)[2][Q], const T (&F)[2][3], 
     T rd[2], j[2][3], m[2][Q], xid[3];
     for (int l = 0; l < 2; l++) component_modes(d[l], rd[l], j[l], m[l]);
     common_velocity(rd, j, F, z, c, u, xid);
-    for (int l = 0; l < 2; l++) relax_component(l, rd[l], j[l], m[l], F[l], u, xid, z, c, out[l]);
+    for (int l = 0; l < 2; l++) {
+        T zl[16];
+        for (int k = 0; k < 16; k++) zl[k] = z[16 * l + k];
+        relax_component(c.rho0[l], l == 0 ? T(1) : T(-1), rd[l], j[l], m[l], F[l], u, xid, zl, c,
+                        out[l]);
+    }
 }
 
 }  // namespace lbm

@@ -1,12 +1,13 @@
 // Device-side data layout of the library (workspace contents).
 //
-// Populations: two ping-pong buffers; replica r owns a block of 38 N_r
-// elements laid out [component][direction][z][y][x] (x fastest).  A buffer
-// holds the post-collision values f*_i(x) of the last step at their source
-// node (pull scheme); a value whose link ends in a wall or a particle node is
-// stored already bounced (moving-wall term applied).  Elements are stored as
-// deviations from w_i rho0_l (FP64, FP32) or as relative deviations
-// (f - w_i rho0_l) / (w_i rho0_l) (FP16).
+// Populations: two ping-pong buffers; replica r owns a block of 38 NP_r
+// elements laid out [component][direction][z+1][y+1][x+1] on its lattice
+// padded by one ghost layer per side (x fastest).  A buffer holds the
+// post-collision values f*_i of the last step in the slot each node pulls
+// from (slot i at padded position x - c_i); values that reach a node by
+// bounce-back or across a periodic face are written there by their
+// producer.  Elements are stored as deviations from w_i rho0_l (FP64, FP32)
+// or as relative deviations (f - w_i rho0_l) / (w_i rho0_l) (FP16).
 #pragma once
 #include <stdint.h>
 
@@ -16,7 +17,8 @@ struct RepDesc {
     int32_t nx, ny, nz;
     uint32_t walls;          // bit0 x, bit1 y, bit2 z
     int64_t N;               // nodes
-    int64_t pop_off;         // element offset of the replica block in a population buffer
+    int64_t NP;              // padded nodes (nx + 2)(ny + 2)(nz + 2)
+    int64_t pop_off;         // element offset of the replica block (38 NP) in a population buffer
     int32_t ty;              // rows (y) per main-kernel tile; tiles span full x rows
     int32_t nty, nchunk;     // tiles along y, z-chunks
     int32_t wg_begin;        // first main-kernel workgroup of this replica
@@ -51,7 +53,7 @@ struct RepState {
     double pad0;
     int64_t step, n_cov, n_unc, n_links;
     int32_t org[3];          // origin of the bbox arrays written for step n
-    int32_t local_read;      // 1: populations of step n sit in their own slots
+    int32_t pad_org;
     uint32_t flags;          // bit0 unstable
     uint32_t k3_done;        // particle-kernel completion counter
     uint32_t pad1[2];
@@ -64,12 +66,8 @@ struct RepState {
 };
 
 constexpr uint32_t FLAG_UNSTABLE = 1u;
-// Node mask of a bounding-box node for one step: bit i (1..18) = the pull of
-// direction i bounces (x - c_i is a particle node at X^{n-1}); MASK_SOLID =
-// particle node at X^n; MASK_LOCAL = uncovered at this step (populations in
-// the node's own slots).
+// Node flag of a bounding-box node for one step: MASK_SOLID = particle node at X^n.
 constexpr uint32_t MASK_SOLID = 1u << 19;
-constexpr uint32_t MASK_LOCAL = 1u << 20;
 constexpr int PART = 16;     // doubles per workgroup partial
 
 }  // namespace lbm
