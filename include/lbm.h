@@ -68,7 +68,9 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };
 /* One replica of the problem (Sec. 3 set-up: square channel, sphere at the
  * centre of the cross-section, body force along z). */
 typedef struct lbm_params {
-    int32_t nx, ny, nz;        /* nodes per axis, 2 <= n, nx <= 256                       */
+    int32_t nx, ny, nz;        /* nodes per axis, 2 <= n, nx <= 256; with NP =            */
+                               /* (nx+2)(ny+2)(nz+2): 38 NP < 2^31 and 19 NP bytes(elem)  */
+                               /* < 2^32 (FP64: NP < 28.2M, FP32/FP16: NP < 56.5M)         */
     uint32_t walls;            /* bit0 x, bit1 y, bit2 z walls; other axes periodic       */
     double rho0[2];            /* reference densities of A (majority) and B               */
     double init_amp;           /* initial densities rho0_l + init_amp (2u - 1), u uniform */

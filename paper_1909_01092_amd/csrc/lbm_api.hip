@@ -110,8 +110,12 @@ std::string validate(const lbm_params *p, int n, int prec) {
         const int nn[3] = {q.nx, q.ny, q.nz};
         if (q.nx < 2 || q.ny < 2 || q.nz < 2) return fmt("replica %d: every axis needs >= 2 nodes", r);
         if (q.nx > MAIN_BLOCK_MIN) return fmt("replica %d: nx = %d exceeds %d", r, q.nx, MAIN_BLOCK_MIN);
-        if ((int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2) >= (int64_t(1) << 31) / 38)
-            return fmt("replica %d: lattice too large for one replica", r);
+        // element offsets of a replica block (38 NP) are 32-bit signed, byte
+        // offsets within one component (19 NP elements) 32-bit unsigned
+        const int64_t np = (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
+        const int64_t es = prec == LBM_FP64 ? 8 : prec == LBM_FP32 ? 4 : 2;
+        if (np >= (int64_t(1) << 31) / 38 || 19 * np * es >= (int64_t(1) << 32))
+            return fmt("replica %d: lattice too large for one replica at this precision", r);
         if (q.walls > 7u) return fmt("replica %d: walls must be a 3-bit mask", r);
         if (!(q.rho0[0] > 0.0) || !(q.rho0[1] > 0.0)) return fmt("replica %d: rho0 must be > 0", r);
         if (!(q.init_amp >= 0.0) || q.init_amp >= std::min(q.rho0[0], q.rho0[1]))

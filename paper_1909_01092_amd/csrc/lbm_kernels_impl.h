@@ -209,28 +209,6 @@ __device__ __forceinline__ void pull_node(const PullCtx<S, T> &c, uint32_t own, 
     }
 }
 
-// Where the post-collision value f*_i of box node (x, y, z) must also be
-// written when its link leaves the box: into the wall ghost x + c_i, slot
-// opp(i) (half-way bounce-back), or, across periodic faces only, into the
-// ghost wrap(x + c_i) - c_i, slot i.  Returns false for links inside the box.
-__device__ __forceinline__ bool exit_slot(int i, int x, int y, int z, const Geo &g, uint32_t &pos,
-                                          int &slot) {
-    const int tx = x + cx(i), ty = y + cy(i), tz = z + cz(i);
-    const bool ox = tx < 0 || tx >= g.nx, oy = ty < 0 || ty >= g.ny, oz = tz < 0 || tz >= g.nz;
-    if (!(ox || oy || oz)) return false;
-    if ((ox && g.wx) || (oy && g.wy) || (oz && g.wz)) {
-        pos = pidx(tx, ty, tz, g);
-        slot = opp(i);
-    } else {
-        const int wx = ox ? (tx < 0 ? tx + g.nx : tx - g.nx) : tx;
-        const int wy = oy ? (ty < 0 ? ty + g.ny : ty - g.ny) : ty;
-        const int wz = oz ? (tz < 0 ? tz + g.nz : tz - g.nz) : tz;
-        pos = pidx(wx - cx(i), wy - cy(i), wz - cz(i), g);
-        slot = i;
-    }
-    return true;
-}
-
 // What a collision needs from the pulled populations of a node: density
 // deviations, momenta and (unless every relaxation time is 1, when the
 // post-collision state depends on density and momentum only) modes 4..18.
@@ -312,8 +290,15 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
 // current plane collides.  The sphere enters only through the solid flags
 // and wetting-layer densities of its bounding box; every FP64 particle
 // computation lives in the bounding-box kernels.
+// FP32 storage with all relaxation times 1: both components unrolled and the
+// kernel held to 128 VGPRs (four waves per SIMD).  Other forms keep the
+// component loop rolled and their natural register allocation.
+template <typename S, typename T, bool TAU1>
+constexpr bool main_fast_form = sizeof(S) == 4 && sizeof(T) == 4 && TAU1;
+
 template <typename S, typename T, int B, bool TAU1>
-__global__ __launch_bounds__(B) void k_main(MainArgs a) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(main_fast_form<S, T, TAU1> ? 4 : 1)))
+void k_main(MainArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *lds = reinterpret_cast<T *>(smem);
 
@@ -406,7 +391,7 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
     };
 
     const int xm = mirror1(x - 1, nx, g.wx), xp = mirror1(x + 1, nx, g.wx);
-    const bool xedge = x == 0 || x == nx - 1, yedge = y == 0 || y == g.ny - 1;
+    const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == g.ny - 1;
 
     // plane zp is filled while plane zp - 1 collides
     for (int zp = z0 - 1; zp <= z1; zp++) {
@@ -458,8 +443,8 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
             if (cf.noise) noise_block<T>(node, step, 8u, k0, k1, zz + 32);
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
-            const bool edge = xedge || yedge || z == 0 || z == g.nz - 1;
-#pragma unroll 1
+            const bool zlo = z == 0, zhi = z == g.nz - 1;
+#pragma unroll (main_fast_form<S, T, TAU1> ? 2 : 1)
             for (int l = 0; l < 2; l++) {
                 // this component's values (selected, so nothing is indexed by l)
                 const T rdl = l ? rd[1] : rd[0];
@@ -487,22 +472,31 @@ __global__ __launch_bounds__(B) void k_main(MainArgs a) {
                 }
                 const T sc = Rel<S>::value ? r0l : T(1);
                 S *dl_base = dst + l * Q * (int32_t)NP;
+                const uint32_t own4 = own * (uint32_t)sizeof(S);
 #pragma unroll
                 for (int i = 0; i < Q; i++) {
                     const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
-                    st_dev<S, T>(&at(dl_base + i * (int32_t)NP, own * (uint32_t)sizeof(S)), out[i], inv);
-                }
-            }
-            // links that leave the box: copy the stored value into the ghost
-            // slot its receiver pulls from (bounce-back or periodic image)
-            if (edge) {
-#pragma unroll 1
-                for (int i = 1; i < Q; i++) {
-                    uint32_t pos;
-                    int slot;
-                    if (!exit_slot(i, x, y, z, g, pos, slot)) continue;
-                    for (int l = 0; l < 2; l++)
-                        dst[(uint32_t)(l * Q + slot) * NP + pos] = dst[(uint32_t)(l * Q + i) * NP + own];
+                    S *col = dl_base + i * (int32_t)NP;
+                    st_dev<S, T>(&at(col, own4), out[i], inv);
+                    if (i == 0) continue;
+                    // a link that leaves the box also writes its value where the
+                    // receiver pulls it from: the wall ghost x + c_i, slot opp(i)
+                    // (half-way bounce-back), or the periodic image of x, slot i
+                    const bool ex = cx(i) > 0 ? xhi : (cx(i) < 0 ? xlo : false);
+                    const bool ey = cy(i) > 0 ? yhi : (cy(i) < 0 ? ylo : false);
+                    const bool ez = cz(i) > 0 ? zhi : (cz(i) < 0 ? zlo : false);
+                    if (ex || ey || ez) {
+                        // element index from the component base: slot * NP + target,
+                        // never negative (x + c_i lies in the ghost layer, the
+                        // periodic image x - n c_i inside the box)
+                        const bool bounce = (ex && g.wx) || (ey && g.wy) || (ez && g.wz);
+                        const int32_t so = bounce ? opp(i) * (int32_t)NP + doff(i, g)
+                                                  : i * (int32_t)NP + (ex ? -cx(i) * nx : 0) +
+                                                        (ey ? -cy(i) * g.ny * g.PX : 0) +
+                                                        (ez ? -cz(i) * g.nz * g.PX * g.PY : 0);
+                        const uint32_t e = (uint32_t)((int32_t)own + so);
+                        st_dev<S, T>(&at(dl_base, e * (uint32_t)sizeof(S)), out[i], inv);
+                    }
                 }
             }
         }
@@ -541,54 +535,75 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
         int bb[3], p[3];
         const bool in = bbox_pos(b, org, Sx, g, bb, p);
         if (in && !(pmask[b] & MASK_SOLID)) {
-            const double X[3] = {st.X[0], st.X[1], st.X[2]};
-            const double U[3] = {st.U[0], st.U[1], st.U[2]};
-            const double W[3] = {st.W[0], st.W[1], st.W[2]};
-            const double rA = rho_n[b], rB = rho_n[S3 + b];
-            const uint32_t own = pidx(p[0], p[1], p[2], g);
+            // neighbour flags, then every value a link needs, all loads in
+            // flight together before the first store
+            uint32_t links = 0;
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-                if (qx < 0 || qy < 0 || qz < 0 || qx >= Sx || qy >= Sx || qz >= Sx) continue;
-                const int qb = (qz * Sx + qy) * Sx + qx;
-                if (!(pmask[qb] & MASK_SOLID)) continue;
-                const double rr[3] = {sepd(p[0] + 0.5 * cx(i) - X[0], g.nx, g.wx),
-                                      sepd(p[1] + 0.5 * cy(i) - X[1], g.ny, g.wy),
-                                      sepd(p[2] + 0.5 * cz(i) - X[2], g.nz, g.wz)};
-                const double ub[3] = {U[0] + W[1] * rr[2] - W[2] * rr[1],
-                                      U[1] + W[2] * rr[0] - W[0] * rr[2],
-                                      U[2] + W[0] * rr[1] - W[1] * rr[0]};
-                const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-                const double rl[2] = {rA, rB};
-                // padded position x + c_i (a ghost when the link crosses a periodic face)
-                const uint32_t tgt = own + (uint32_t)doff(i, g);
-                double mom = 0.0;
+                const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
+                const int qb = inb ? (qz * Sx + qy) * Sx + qx : b;
+                if (inb && (pmask[qb] & MASK_SOLID)) links |= 1u << i;
+            }
+            if (links) {
+                const double X[3] = {st.X[0], st.X[1], st.X[2]};
+                const double U[3] = {st.U[0], st.U[1], st.U[2]};
+                const double W[3] = {st.W[0], st.W[1], st.W[2]};
+                const double rA = rho_n[b], rB = rho_n[S3 + b];
+                const double dA = st.delta[0], dB = st.delta[1];
+                const uint32_t own = pidx(p[0], p[1], p[2], g);
+                double fs[2][Q], vA[Q], vB[Q];
 #pragma unroll
-                for (int l = 0; l < 2; l++) {
-                    const double wr = wgt(i) * D.rho0[l];
-                    const T sc = Rel<S>::value ? T(wr) : T(1);
-                    const double fs =
-                        wr + (double)ld_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + own), sc);
-                    const double corr = 6.0 * wgt(i) * rl[l] * cu;
-                    mom += 2.0 * fs - corr;
-                    acc[6 + l] -= corr;
-                    st_dev<S, T>(buf + ((uint32_t)(l * Q + opp(i)) * NP + tgt), T(fs - corr - wr),
-                                 Rel<S>::value ? T(1.0 / wr) : T(1));
+                for (int i = 1; i < Q; i++) {
+                    fs[0][i] = fs[1][i] = vA[i] = vB[i] = 0.0;
+                    if (!((links >> i) & 1u)) continue;
+                    const int qb = ((bb[2] + cz(i)) * Sx + bb[1] + cy(i)) * Sx + bb[0] + cx(i);
+#pragma unroll
+                    for (int l = 0; l < 2; l++) {
+                        const double wr = wgt(i) * D.rho0[l];
+                        const T sc = Rel<S>::value ? T(wr) : T(1);
+                        fs[l][i] = wr + (double)ld_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + own), sc);
+                    }
+                    vA[i] = vrho[qb];
+                    vB[i] = vrho[S3 + qb];
                 }
-                const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
-                acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
-                acc[3] += rr[1] * lp[2] - rr[2] * lp[1];
-                acc[4] += rr[2] * lp[0] - rr[0] * lp[2];
-                acc[5] += rr[0] * lp[1] - rr[1] * lp[0];
-                acc[14] += 1.0;
-                // wetting-layer reaction: the fluid's Shan-Chen force from this particle node
-                const double s = -D.G * wgt(i) * (rA * (vrho[S3 + qb] + st.delta[1]) +
-                                                  rB * (vrho[qb] + st.delta[0]));
-                const double fl[3] = {s * cx(i), s * cy(i), s * cz(i)};
-                acc[8] += fl[0]; acc[9] += fl[1]; acc[10] += fl[2];
-                acc[11] += rr[1] * fl[2] - rr[2] * fl[1];
-                acc[12] += rr[2] * fl[0] - rr[0] * fl[2];
-                acc[13] += rr[0] * fl[1] - rr[1] * fl[0];
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    if (!((links >> i) & 1u)) continue;
+                    const double rr[3] = {sepd(p[0] + 0.5 * cx(i) - X[0], g.nx, g.wx),
+                                          sepd(p[1] + 0.5 * cy(i) - X[1], g.ny, g.wy),
+                                          sepd(p[2] + 0.5 * cz(i) - X[2], g.nz, g.wz)};
+                    const double ub[3] = {U[0] + W[1] * rr[2] - W[2] * rr[1],
+                                          U[1] + W[2] * rr[0] - W[0] * rr[2],
+                                          U[2] + W[0] * rr[1] - W[1] * rr[0]};
+                    const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+                    const double rl[2] = {rA, rB};
+                    // padded position x + c_i (a ghost when the link crosses a periodic face)
+                    const uint32_t tgt = own + (uint32_t)doff(i, g);
+                    double mom = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 2; l++) {
+                        const double wr = wgt(i) * D.rho0[l];
+                        const double corr = 6.0 * wgt(i) * rl[l] * cu;
+                        mom += 2.0 * fs[l][i] - corr;
+                        acc[6 + l] -= corr;
+                        st_dev<S, T>(buf + ((uint32_t)(l * Q + opp(i)) * NP + tgt), T(fs[l][i] - corr - wr),
+                                     Rel<S>::value ? T(1.0 / wr) : T(1));
+                    }
+                    const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
+                    acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
+                    acc[3] += rr[1] * lp[2] - rr[2] * lp[1];
+                    acc[4] += rr[2] * lp[0] - rr[0] * lp[2];
+                    acc[5] += rr[0] * lp[1] - rr[1] * lp[0];
+                    acc[14] += 1.0;
+                    // wetting-layer reaction: the fluid's Shan-Chen force from this particle node
+                    const double sw = -D.G * wgt(i) * (rA * (vB[i] + dB) + rB * (vA[i] + dA));
+                    const double fl[3] = {sw * cx(i), sw * cy(i), sw * cz(i)};
+                    acc[8] += fl[0]; acc[9] += fl[1]; acc[10] += fl[2];
+                    acc[11] += rr[1] * fl[2] - rr[2] * fl[1];
+                    acc[12] += rr[2] * fl[0] - rr[0] * fl[2];
+                    acc[13] += rr[0] * fl[1] - rr[1] * fl[0];
+                }
             }
         }
     }
@@ -719,22 +734,29 @@ __global__ __launch_bounds__(B) void k_particle_a(ParticleArgs a) {
 }
 
 // mean density of the nodes around bbox entry bb that are fluid at X^n and
-// at X^{n+1}; rho0 when there is none
+// at X^{n+1}; rho0 when there is none.  Flags first, then the densities,
+// each group of loads in flight together.
 __device__ __forceinline__ void mean_kept_neighbours(const int (&bb)[3], int Sx, int S3,
                                                      const uint8_t *flags, const double *raw,
                                                      const double *rho0, double (&rb)[2]) {
-    double s0 = 0.0, s1 = 0.0;
-    int cnt = 0;
+    const int self = (bb[2] * Sx + bb[1]) * Sx + bb[0];
+    uint32_t keep = 0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-        if (qx < 0 || qy < 0 || qz < 0 || qx >= Sx || qy >= Sx || qz >= Sx) continue;
-        const int qb = (qz * Sx + qy) * Sx + qx;
-        if ((flags[qb] & 7) != 7) continue;
+        const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
+        const int qb = inb ? (qz * Sx + qy) * Sx + qx : self;
+        if (inb && (flags[qb] & 7) == 7) keep |= 1u << i;
+    }
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (!((keep >> i) & 1u)) continue;
+        const int qb = self + (cz(i) * Sx + cy(i)) * Sx + cx(i);
         s0 += raw[qb];
         s1 += raw[S3 + qb];
-        cnt++;
     }
+    const int cnt = __builtin_popcount(keep);
     rb[0] = cnt > 0 ? s0 / cnt : rho0[0];
     rb[1] = cnt > 0 ? s1 / cnt : rho0[1];
 }
@@ -819,30 +841,46 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
             unc[7] += rb[1];
             unc[9] += 1.0;
         } else if ((f & 1) && !(f & 4)) {  // particle node at X^{n+1}: wetting layer
-            double s0 = 0.0, s1 = 0.0;
-            int cnt = 0;
+            const int self = b;
+            uint32_t kept = 0, fresh = 0;  // fluid at X^{n+1}; of those, uncovered now
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-                if (qx < 0 || qy < 0 || qz < 0 || qx >= Sx || qy >= Sx || qz >= Sx) continue;
-                const int qb = (qz * Sx + qy) * Sx + qx;
-                const int fq = flags[qb];
-                if (!((fq & 1) && (fq & 4))) continue;
-                double r0, r1;
-                if (fq & 2) {
-                    r0 = raw[qb];
-                    r1 = raw[S3 + qb];
-                } else {  // neighbour uncovered at this step: its f_eq density
-                    const int qq[3] = {qx, qy, qz};
-                    double rb[2];
-                    mean_kept_neighbours(qq, Sx, S3, flags, raw, D.rho0, rb);
-                    r0 = rb[0];
-                    r1 = rb[1];
+                const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
+                const int fq = flags[inb ? (qz * Sx + qy) * Sx + qx : self];
+                if (inb && (fq & 1) && (fq & 4)) {
+                    kept |= 1u << i;
+                    if (!(fq & 2)) fresh |= 1u << i;
                 }
-                s0 += r0;
-                s1 += r1;
-                cnt++;
             }
+            double r0[Q], r1[Q];
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                r0[i] = r1[i] = 0.0;
+                if (((kept & ~fresh) >> i) & 1u) {
+                    const int qb = self + (cz(i) * Sx + cy(i)) * Sx + cx(i);
+                    r0[i] = raw[qb];
+                    r1[i] = raw[S3 + qb];
+                }
+            }
+            // a neighbour uncovered at this step carries its f_eq density (rare)
+            for (uint32_t m = fresh; m; m &= m - 1) {
+                const int i = __builtin_ctz(m);
+                const int qq[3] = {bb[0] + cx(i), bb[1] + cy(i), bb[2] + cz(i)};
+                double rb[2];
+                mean_kept_neighbours(qq, Sx, S3, flags, raw, D.rho0, rb);
+#pragma unroll
+                for (int k = 1; k < Q; k++)
+                    if (k == i) { r0[k] = rb[0]; r1[k] = rb[1]; }
+            }
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                if (!((kept >> i) & 1u)) continue;
+                s0 += r0[i];
+                s1 += r1[i];
+            }
+            const int cnt = __builtin_popcount(kept);
             vrho[b] = cnt > 0 ? s0 / cnt + D.drho : 0.0;
             vrho[S3 + b] = cnt > 0 ? s1 / cnt - D.drho : 0.0;
         }

@@ -88,3 +88,17 @@ def test_init_rejects_bad_workspace_before_device_work(capi):
     assert L.lbm_init(arr, 1, 1, C.c_void_p(4096), need - 1, None, C.byref(ctx)) == capi.LBM_ENOMEM
     assert L.lbm_init(arr, 1, 7, C.c_void_p(4096), need, None, C.byref(ctx)) == capi.LBM_EINVAL
     assert not ctx.value
+
+
+def test_lattice_size_limit_depends_on_precision(capi):
+    """Byte offsets within one component block are 32-bit: a lattice of about
+    36M padded nodes fits FP32 and FP16 storage but not FP64."""
+    from paper_1909_01092_amd.sim import workspace_bytes
+    q = dict(nx=190, ny=190, nz=1000, walls=3)
+    assert workspace_bytes(q, "fp32") > 0
+    assert workspace_bytes(q, "fp16") > 0
+    with pytest.raises(capi.LbmError) as e:
+        workspace_bytes(q, "fp64")
+    assert e.value.code == capi.LBM_EINVAL and b"too large" in str(e.value).encode()
+    with pytest.raises(capi.LbmError):
+        workspace_bytes(dict(nx=200, ny=200, nz=1500, walls=3), "fp32")
