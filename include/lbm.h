@@ -83,7 +83,9 @@ typedef struct lbm_params {
     int32_t force_mode;        /* 0: sphere gets F_p = V (rho_p - rho_tot0) g (eq. fp),
                                      fluid gets -F_p / M_fluid (net zero); 1: fluid rho g,
                                      sphere rho_p V g                                       */
-    double radius;             /* sphere radius d/2 (<= 0: no sphere)                     */
+    double radius;             /* sphere radius d/2 (<= 0: no sphere); a periodic axis     */
+                               /* needs n >= 2 ceil(R) + 6, a wall axis one node of       */
+                               /* clearance around the initial sphere                     */
     double rho_p;              /* sphere density                                          */
     double wet_drho;           /* wetting-layer offset Delta rho (+A, -B)                 */
     double X0[3], U0[3], W0[3];/* initial centre, velocity, angular velocity              */

@@ -33,12 +33,11 @@ size_t elem_size(int prec) { return prec == LBM_FP64 ? 8 : prec == LBM_FP32 ? 4 
 bool has_sphere(const lbm_params &p) { return p.radius > 0.0; }
 
 int bbox_edge(const lbm_params &p) {
-    return has_sphere(p) ? 2 * (int)std::ceil(p.radius) + 7 : 0;
+    return has_sphere(p) ? 2 * (int)std::ceil(p.radius) + 6 : 0;
 }
 
 struct Layout {
-    size_t tables, desc, state, pop[2], part1, part3, part3b, raw, vrho, rho_n, pmask, flags, series, aux,
-        total;
+    size_t tables, desc, state, pop[2], part1, part3, raw, vrho, rho_n, pmask, series, aux, total;
     std::vector<int64_t> pop_off, bbox_off, part3_off, series_off, init_wg;
     std::vector<int> S, k3_count;
     int64_t Ntot = 0, NPtot = 0, S3tot = 0, part3_tot = 0, series_tot = 0, init_tot = 0;
@@ -80,12 +79,10 @@ Layout plan(const lbm_params *p, int n, int prec) {
     L.pop[1] = take(38 * L.NPtot * es);
     L.part1 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
     L.part3 = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
-    L.part3b = take(sizeof(double) * std::max<int64_t>(L.part3_tot, 1));
-    L.raw = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
+    L.raw = take(sizeof(double) * std::max<int64_t>(RAW * L.S3tot, 1));
     L.vrho = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
     L.rho_n = take(sizeof(double) * std::max<int64_t>(2 * L.S3tot, 1));
     L.pmask = take(sizeof(uint32_t) * std::max<int64_t>(L.S3tot, 1));
-    L.flags = take(std::max<int64_t>(L.S3tot, 1));
     L.series = take(sizeof(double) * std::max<int64_t>(L.series_tot, 1));
     L.aux = take(sizeof(double) * L.aux_doubles);
     L.total = o;
@@ -140,7 +137,7 @@ std::string validate(const lbm_params *p, int n, int prec) {
                     if (q.X0[a] - q.radius < 1.0 || q.X0[a] + q.radius > nn[a] - 2.0)
                         return fmt("replica %d: sphere needs one node of clearance from the walls on axis %d", r, a);
                 } else {
-                    if (S > nn[a]) return fmt("replica %d: periodic axis %d shorter than 2 ceil(R) + 7", r, a);
+                    if (S > nn[a]) return fmt("replica %d: periodic axis %d shorter than 2 ceil(R) + 6", r, a);
                     if (q.X0[a] < 0.0 || q.X0[a] >= nn[a]) return fmt("replica %d: X0 outside the box", r);
                 }
                 if (!(std::fabs(q.U0[a]) < 0.5)) return fmt("replica %d: |U0| must be < 0.5", r);
@@ -180,12 +177,10 @@ struct lbm_ctx {
     void *d_pop(int k) { return ws + L.pop[k]; }
     double *d_part1() { return reinterpret_cast<double *>(ws + L.part1); }
     double *d_part3() { return reinterpret_cast<double *>(ws + L.part3); }
-    double *d_part3b() { return reinterpret_cast<double *>(ws + L.part3b); }
     double *d_raw() { return reinterpret_cast<double *>(ws + L.raw); }
     double *d_vrho() { return reinterpret_cast<double *>(ws + L.vrho); }
     double *d_rho_n() { return reinterpret_cast<double *>(ws + L.rho_n); }
     uint32_t *d_pmask() { return reinterpret_cast<uint32_t *>(ws + L.pmask); }
-    uint8_t *d_flags() { return reinterpret_cast<uint8_t *>(ws + L.flags); }
     double *d_series() { return reinterpret_cast<double *>(ws + L.series); }
     double *d_aux() { return reinterpret_cast<double *>(ws + L.aux); }
 };
@@ -291,9 +286,9 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     la.k3_begin = c->d_tables() + (c->nrep + 1);
     la.nrep = c->nrep;
     la.buf = c->d_pop(1 - c->cur);
-    la.pmask = c->d_pmask();
     la.vrho = c->d_vrho();
     la.rho_n = c->d_rho_n();
+    la.raw = c->d_raw();
     la.part1 = c->d_part1();
     e = launch_links(c->prec, la, c->k3_grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "link kernel launch");
@@ -305,10 +300,8 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     pa.buf = c->d_pop(1 - c->cur);
     pa.part1 = c->d_part1();
     pa.part3 = c->d_part3();
-    pa.part3b = c->d_part3b();
     pa.pmask = c->d_pmask();
     pa.raw = c->d_raw();
-    pa.flags = c->d_flags();
     pa.vrho = c->d_vrho();
     pa.series = c->d_series();
     e = launch_particle(c->prec, pa, c->k3_grid, c->stream);

@@ -25,10 +25,10 @@ struct LinkArgs {
     const RepState *state;
     const int32_t *k3_begin;
     int32_t nrep;
-    void *buf;                 // post-collision populations of step n (pre-bounced here)
-    const uint32_t *pmask;
-    const double *vrho;
-    const double *rho_n;
+    void *buf;                 // post-collision populations of step n (bounced values written)
+    const double *vrho;        // wetting-layer densities of step n (bbox)
+    const double *rho_n;       // densities of step n (bbox)
+    double *raw;               // post-streaming densities and momenta of fluid box nodes, written
     double *part1;             // per-workgroup link partials
 };
 
@@ -37,14 +37,12 @@ struct ParticleArgs {
     RepState *state;
     const int32_t *k3_begin;
     int32_t nrep;
-    void *buf;                 // post-collision populations of step n
+    void *buf;                 // populations of step n+1 (uncovered-node values written)
     const double *part1;       // link partials
-    double *part3;             // covered-node partials
-    double *part3b;            // uncovered-node partials
+    double *part3;             // cover / uncover partials
     uint32_t *pmask;           // node masks of step n+1, written
-    double *raw;
-    uint8_t *flags;
-    double *vrho;
+    const double *raw;
+    double *vrho;              // wetting-layer densities of step n+1, written
     double *series;
 };
 

@@ -20,8 +20,8 @@
 // slots they pull from.  Every pull is therefore 38 loads at wave-uniform
 // offsets from the node's own index.
 //
-// One step = k_main (all nodes of all replicas) + k_links + k_particle_a +
-// k_particle_b (bounding box of each sphere).
+// One step = k_main (all nodes of all replicas) + k_links + k_particle
+// (bounding box of each sphere).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -304,7 +304,7 @@ void k_main(MainArgs a) {
 
     const int wg = xcd_logical(blockIdx.x, gridDim.x);
     const int r = find_rep(a.wg_begin, a.nrep, wg);
-    const RepDesc &D = a.desc[r];
+    const RepDesc D = a.desc[r];  // by value: no reload after stores
     RepState *stp = a.state + r;
     const Geo g = geo_of(D);
     const int nx = g.nx, ty = D.ty, zc = D.cz;
@@ -444,7 +444,8 @@ void k_main(MainArgs a) {
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
             const bool zlo = z == 0, zhi = z == g.nz - 1;
-#pragma unroll (main_fast_form<S, T, TAU1> ? 2 : 1)
+            constexpr int kCompUnroll = main_fast_form<S, T, TAU1> ? 2 : 1;
+#pragma unroll kCompUnroll
             for (int l = 0; l < 2; l++) {
                 // this component's values (selected, so nothing is indexed by l)
                 const T rdl = l ? rd[1] : rd[0];
@@ -504,278 +505,315 @@ void k_main(MainArgs a) {
     }
 }
 
-// =============================================================== k_links
-// Links from fluid nodes into the sphere at X^n (one thread per bbox entry):
-// moving-wall bounce-back f_opp(i)(x) = f*_i(x) - 6 w_i rho_l(x) (c_i . u_b)
-// written into the particle node's slot opp(i) at x + c_i (where x pulls it
-// from), momentum exchange sum_l (2 f*_i - 6 w_i rho_l c_i . u_b) c_i with
-// its torque about X^n, the bounce-back mass flux, and the reaction of the
-// wetting layer on the sphere.  Per-workgroup FP64 sums, fixed order.
-template <typename S, typename T, int B>
-__global__ __launch_bounds__(B) void k_links(LinkArgs a) {
-    __shared__ double red[(B / 64) * 16];
-    const int r = find_rep(a.k3_begin, a.nrep, blockIdx.x);
-    const RepDesc &D = a.desc[r];
-    if (!D.has_particle) return;
-    const RepState &st = a.state[r];
-    const Geo g = geo_of(D);
-    const int t = threadIdx.x;
-    const int local = blockIdx.x - D.k3_begin;
-    const int Sx = D.S, S3 = Sx * Sx * Sx;
-    const int32_t org[3] = {st.org[0], st.org[1], st.org[2]};
-    const uint32_t *pmask = a.pmask + D.bbox_off;
-    const double *vrho = a.vrho + D.bbox_off * 2;
-    const double *rho_n = a.rho_n + D.bbox_off * 2;
-    S *buf = reinterpret_cast<S *>(a.buf) + D.pop_off;
-    const uint32_t NP = g.NP;
-    double acc[15];
-    for (int k = 0; k < 15; k++) acc[k] = 0.0;
-    const int b = local * B + t;
-    if (b < S3) {
-        int bb[3], p[3];
-        const bool in = bbox_pos(b, org, Sx, g, bb, p);
-        if (in && !(pmask[b] & MASK_SOLID)) {
-            // neighbour flags, then every value a link needs, all loads in
-            // flight together before the first store
-            uint32_t links = 0;
+// ---------------------------------------------------- sphere-box helpers
+// Sum of NV values over per-workgroup partials [count][PART] starting at k0,
+// in a fixed order independent of the launch: lane l adds partials l, l + 64,
+// ..., then a butterfly over the wave.  Every lane of every wave holds the
+// same result, so no LDS or barrier is needed.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *part, int count, int k0, double (&v)[NV]) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-                const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
-                const int qb = inb ? (qz * Sx + qy) * Sx + qx : b;
-                if (inb && (pmask[qb] & MASK_SOLID)) links |= 1u << i;
-            }
-            if (links) {
-                const double X[3] = {st.X[0], st.X[1], st.X[2]};
-                const double U[3] = {st.U[0], st.U[1], st.U[2]};
-                const double W[3] = {st.W[0], st.W[1], st.W[2]};
-                const double rA = rho_n[b], rB = rho_n[S3 + b];
-                const double dA = st.delta[0], dB = st.delta[1];
-                const uint32_t own = pidx(p[0], p[1], p[2], g);
-                double fs[2][Q], vA[Q], vB[Q];
+    for (int k = 0; k < NV; k++) v[k] = 0.0;
+    for (int w = lane; w < count; w += 64) {
+        const double *p = part + (int64_t)w * PART + k0;
 #pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    fs[0][i] = fs[1][i] = vA[i] = vB[i] = 0.0;
-                    if (!((links >> i) & 1u)) continue;
-                    const int qb = ((bb[2] + cz(i)) * Sx + bb[1] + cy(i)) * Sx + bb[0] + cx(i);
-#pragma unroll
-                    for (int l = 0; l < 2; l++) {
-                        const double wr = wgt(i) * D.rho0[l];
-                        const T sc = Rel<S>::value ? T(wr) : T(1);
-                        fs[l][i] = wr + (double)ld_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + own), sc);
-                    }
-                    vA[i] = vrho[qb];
-                    vB[i] = vrho[S3 + qb];
-                }
-#pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    if (!((links >> i) & 1u)) continue;
-                    const double rr[3] = {sepd(p[0] + 0.5 * cx(i) - X[0], g.nx, g.wx),
-                                          sepd(p[1] + 0.5 * cy(i) - X[1], g.ny, g.wy),
-                                          sepd(p[2] + 0.5 * cz(i) - X[2], g.nz, g.wz)};
-                    const double ub[3] = {U[0] + W[1] * rr[2] - W[2] * rr[1],
-                                          U[1] + W[2] * rr[0] - W[0] * rr[2],
-                                          U[2] + W[0] * rr[1] - W[1] * rr[0]};
-                    const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-                    const double rl[2] = {rA, rB};
-                    // padded position x + c_i (a ghost when the link crosses a periodic face)
-                    const uint32_t tgt = own + (uint32_t)doff(i, g);
-                    double mom = 0.0;
-#pragma unroll
-                    for (int l = 0; l < 2; l++) {
-                        const double wr = wgt(i) * D.rho0[l];
-                        const double corr = 6.0 * wgt(i) * rl[l] * cu;
-                        mom += 2.0 * fs[l][i] - corr;
-                        acc[6 + l] -= corr;
-                        st_dev<S, T>(buf + ((uint32_t)(l * Q + opp(i)) * NP + tgt), T(fs[l][i] - corr - wr),
-                                     Rel<S>::value ? T(1.0 / wr) : T(1));
-                    }
-                    const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
-                    acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
-                    acc[3] += rr[1] * lp[2] - rr[2] * lp[1];
-                    acc[4] += rr[2] * lp[0] - rr[0] * lp[2];
-                    acc[5] += rr[0] * lp[1] - rr[1] * lp[0];
-                    acc[14] += 1.0;
-                    // wetting-layer reaction: the fluid's Shan-Chen force from this particle node
-                    const double sw = -D.G * wgt(i) * (rA * (vB[i] + dB) + rB * (vA[i] + dA));
-                    const double fl[3] = {sw * cx(i), sw * cy(i), sw * cz(i)};
-                    acc[8] += fl[0]; acc[9] += fl[1]; acc[10] += fl[2];
-                    acc[11] += rr[1] * fl[2] - rr[2] * fl[1];
-                    acc[12] += rr[2] * fl[0] - rr[0] * fl[2];
-                    acc[13] += rr[0] * fl[1] - rr[1] * fl[0];
-                }
-            }
-        }
+        for (int k = 0; k < NV; k++) v[k] += p[k];
     }
-    block_sum<B, 15>(acc, red);
-    if (t == 0) {
-        double *p = a.part1 + D.part3_off + (int64_t)local * PART;
-        for (int k = 0; k < 15; k++) p[k] = acc[k];
-    }
+    wave_sum<NV>(v);
 }
 
-// =========================================================== k_particle_a
-// Per replica, one thread per node of the sphere's new bounding box.  Every
-// workgroup redundantly reduces the link partials (fixed order) and advances
-// the sphere (leap-frog Newton-Euler under F = links - wetting reaction +
-// F_ext + pending event momentum); workgroup 0 records the update.  Each
-// thread then flags its node for step n+1 and, for nodes fluid at X^n, pulls
-// the step-(n+1) populations: densities for the wetting layer and uncovered
-// nodes, momentum and mass of the nodes the sphere covers.
-template <typename S, typename T, int B>
-__global__ __launch_bounds__(B) void k_particle_a(ParticleArgs a) {
-    __shared__ double red[(B / 64) * 16];
-    const int wg = blockIdx.x;
-    const int r = find_rep(a.k3_begin, a.nrep, wg);
-    const RepDesc &D = a.desc[r];
-    if (!D.has_particle) return;
-    RepState *st = a.state + r;
-    const Geo g = geo_of(D);
-    const int t = threadIdx.x;
-    const int local = wg - D.k3_begin;
+// Neighbourhood of a box node p for the particle predicate: along each axis
+// the three positions p + {-1, 0, 1} (wrapped on periodic axes, flagged
+// outside on wall axes) with their squared minimum-image separations from a
+// centre.  pnode_nb combines them in the order pnode uses, so the decision
+// for a neighbour is bitwise the one pnode takes for it.
+struct Nbr {
+    double s[3][3];   // [axis][c + 1] squared separation
+    bool ok[3][3];    // position inside the lattice (not a wall layer)
+};
 
-    double X[3], U[3], Wv[3];
-    for (int q = 0; q < 3; q++) { X[q] = st->X[q]; U[q] = st->U[q]; Wv[q] = st->W[q]; }
-    // 1. link momentum exchange and wetting-layer reaction of step n
-    double sum[15];
-    for (int k = 0; k < 15; k++) sum[k] = 0.0;
-    for (int w = t; w < D.k3_count; w += B) {
-        const double *p = a.part1 + D.part3_off + (int64_t)w * PART;
-        for (int q = 0; q < 15; q++) sum[q] += p[q];
-    }
-    block_sum<B, 15>(sum, red);
-    // 2. Newton-Euler, leap-frog
-    double F[3], Tq[3], Un[3], Wn[3], Xn[3];
+__device__ __forceinline__ void nbr_of(const int (&p)[3], const double *Xc, const Geo &g, Nbr &nb) {
+#pragma clang fp contract(off)
     const int n3[3] = {g.nx, g.ny, g.nz};
     const bool w3[3] = {g.wx, g.wy, g.wz};
-    for (int q = 0; q < 3; q++) {
-        F[q] = sum[q] - sum[8 + q] + D.Fext[q] + st->Pev[q];
-        Tq[q] = sum[3 + q] - sum[11 + q] + st->Lev[q];
-        Un[q] = D.fixed_velocity ? U[q] : U[q] + F[q] / D.mp;
-        Wn[q] = D.fixed_velocity ? Wv[q] : Wv[q] + Tq[q] / D.Ip;
-    }
-    for (int q = 0; q < 3; q++) {
-        Xn[q] = X[q] + Un[q];
-        if (!w3[q]) {
-            if (Xn[q] >= n3[q]) Xn[q] -= n3[q];
-            else if (Xn[q] < 0.0) Xn[q] += n3[q];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            int q = p[ax] + k - 1;
+            nb.ok[ax][k] = w3[ax] ? (q >= 0 && q < n3[ax]) : true;
+            if (!w3[ax]) q = q < 0 ? q + n3[ax] : (q >= n3[ax] ? q - n3[ax] : q);
+            const double d = sepd((double)q - Xc[ax], n3[ax], w3[ax]);
+            nb.s[ax][k] = d * d;
         }
-    }
-    // 3. bounding box of X^n and X^{n+1}
-    int org[3];
-    for (int q = 0; q < 3; q++) {
-        double lo = X[q];
-        double xn = Xn[q];
-        if (!w3[q]) {  // unwrap X^{n+1} next to X^n
-            if (xn - lo > 0.5 * n3[q]) xn -= n3[q];
-            else if (lo - xn > 0.5 * n3[q]) xn += n3[q];
-        }
-        lo = fmin(lo, xn);
-        org[q] = (int)floor(lo - D.radius) - 2;
-    }
-    if (local == 0 && t == 0) {
-        for (int q = 0; q < 3; q++) {
-            st->Xn[q] = Xn[q]; st->Un[q] = Un[q]; st->Wn[q] = Wn[q];
-            st->Fn[q] = F[q]; st->Tn[q] = Tq[q]; st->orgn[q] = org[q];
-        }
-        st->dMbb[0] = sum[6];
-        st->dMbb[1] = sum[7];
-        st->nlinks = sum[14];
-    }
-    const int Sx = D.S, S3 = Sx * Sx * Sx;
-    double *raw = a.raw + D.bbox_off * 2;
-    uint8_t *flags = a.flags + D.bbox_off;
-    uint32_t *pmask = a.pmask + D.bbox_off;
-    const PullCtx<S, T> pc = pull_ctx<S, T>(a.buf, D, g);
-
-    // 4. solid flags of step n+1; covered nodes (fluid at X^n, particle at
-    // X^{n+1}) with the momentum of their step-(n+1) populations
-    double cov[10];
-    for (int k = 0; k < 10; k++) cov[k] = 0.0;
-    const int b = local * B + t;
-    if (b < S3) {
-        int bb[3], p[3];
-        const bool in = bbox_pos(b, org, Sx, g, bb, p);
-        const bool fo = in && !pnode(p[0], p[1], p[2], X, D.R2, g);
-        const bool fn = in && !pnode(p[0], p[1], p[2], Xn, D.R2, g);
-        pmask[b] = (in && !fn) ? MASK_SOLID : 0u;
-        if (fo) {
-            T d[2][Q];
-            pull_node(pc, pidx(p[0], p[1], p[2], g), d);
-            double jt[3] = {0.0, 0.0, 0.0}, rho[2];
-            for (int l = 0; l < 2; l++) {
-                T rd, jl[3], mm[Q];
-                component_modes(d[l], rd, jl, mm);
-                rho[l] = D.rho0[l] + (double)rd;
-                for (int q = 0; q < 3; q++) jt[q] += (double)jl[q];
-            }
-            raw[b] = rho[0];
-            raw[S3 + b] = rho[1];
-            if (!fn) {
-                const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
-                                      sepd(p[2] - Xn[2], g.nz, g.wz)};
-                cov[0] += jt[0]; cov[1] += jt[1]; cov[2] += jt[2];
-                cov[3] += rr[1] * jt[2] - rr[2] * jt[1];
-                cov[4] += rr[2] * jt[0] - rr[0] * jt[2];
-                cov[5] += rr[0] * jt[1] - rr[1] * jt[0];
-                cov[6] += rho[0];
-                cov[7] += rho[1];
-                cov[9] += 1.0;
-            }
-        }
-        if (in && !fn) cov[8] += 1.0;
-        flags[b] = (uint8_t)((in ? 1 : 0) | (fo ? 2 : 0) | (fn ? 4 : 0));
-    }
-    block_sum<B, 10>(cov, red);
-    if (t == 0) {
-        double *p = a.part3 + D.part3_off + (int64_t)local * PART;
-        for (int k = 0; k < 10; k++) p[k] = cov[k];
     }
 }
 
-// mean density of the nodes around bbox entry bb that are fluid at X^n and
-// at X^{n+1}; rho0 when there is none.  Flags first, then the densities,
-// each group of loads in flight together.
-__device__ __forceinline__ void mean_kept_neighbours(const int (&bb)[3], int Sx, int S3,
-                                                     const uint8_t *flags, const double *raw,
-                                                     const double *rho0, double (&rb)[2]) {
-    const int self = (bb[2] * Sx + bb[1]) * Sx + bb[0];
+__device__ __forceinline__ bool nbr_ok(const Nbr &nb, int i) {
+    return nb.ok[0][cx(i) + 1] && nb.ok[1][cy(i) + 1] && nb.ok[2][cz(i) + 1];
+}
+
+__device__ __forceinline__ bool pnode_nb(const Nbr &nb, int i, double R2) {
+#pragma clang fp contract(off)
+    double d2 = nb.s[0][cx(i) + 1] + nb.s[1][cy(i) + 1];
+    d2 = d2 + nb.s[2][cz(i) + 1];
+    return d2 < R2;
+}
+
+// box coordinates of lattice node p in the box at org (periodic axes
+// unwrapped next to it); false when p lies outside the box
+__device__ __forceinline__ bool box_coords(const int (&p)[3], const int32_t *org, int S, const Geo &g,
+                                           int (&bb)[3]) {
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    const bool w3[3] = {g.wx, g.wy, g.wz};
+    bool in = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+        int v = p[ax] - org[ax];
+        if (!w3[ax]) { if (v < 0) v += n3[ax]; else if (v >= n3[ax]) v -= n3[ax]; }
+        bb[ax] = v;
+        in = in && v >= 0 && v < S;
+    }
+    return in;
+}
+
+// box index of neighbour p + c_i from p's box coordinates; -1 outside the box
+__device__ __forceinline__ int box_nb(const int (&bb)[3], int i, int S) {
+    const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
+    if (qx < 0 || qy < 0 || qz < 0 || qx >= S || qy >= S || qz >= S) return -1;
+    return (qz * S + qy) * S + qx;
+}
+
+// lattice position of neighbour p + c_i (wrapped on periodic axes)
+__device__ __forceinline__ void nb_pos(const int (&p)[3], int i, const Geo &g, int (&q)[3]) {
+    q[0] = mirror1(p[0] + cx(i), g.nx, false);
+    q[1] = mirror1(p[1] + cy(i), g.ny, false);
+    q[2] = mirror1(p[2] + cz(i), g.nz, false);
+}
+
+// storage form of a deviation (as st_dev writes it) and the value a pull of
+// it returns (as ld_dev reads it with the pull's scale)
+template <typename S, typename T>
+__device__ __forceinline__ T store_round(double v, T inv_scale, T scale, S &sv) {
+    if constexpr (Rel<S>::value) {
+        sv = (S)(float)(T(v) * inv_scale);
+        return T((float)sv) * scale;
+    } else {
+        sv = (S)T(v);
+        return T(sv);
+    }
+}
+
+// Mean post-streaming density of the neighbours of p that are fluid at X^n
+// and at X^{n+1} (raw of the box at orgo); rho0 when there is none.
+__device__ __noinline__ void mean_kept(const int (&p)[3], const double *Xo, const double *Xn, double R2,
+                                          const double *raw, const int32_t *orgo, int Sx, int S3,
+                                          const Geo &g, const double *rho0, double (&rb)[2]) {
+    Nbr no, nn;
+    nbr_of(p, Xo, g, no);
+    nbr_of(p, Xn, g, nn);
+    int bo[3];
+    const bool inbox = box_coords(p, orgo, Sx, g, bo);
+    int idx[Q];
     uint32_t keep = 0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
-        const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-        const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
-        const int qb = inb ? (qz * Sx + qy) * Sx + qx : self;
-        if (inb && (flags[qb] & 7) == 7) keep |= 1u << i;
+        idx[i] = inbox ? box_nb(bo, i, Sx) : -1;
+        if (idx[i] >= 0 && nbr_ok(no, i) && !pnode_nb(no, i, R2) && !pnode_nb(nn, i, R2))
+            keep |= 1u << i;
     }
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (!((keep >> i) & 1u)) continue;
-        const int qb = self + (cz(i) * Sx + cy(i)) * Sx + cx(i);
-        s0 += raw[qb];
-        s1 += raw[S3 + qb];
+        s0 += raw[idx[i]];
+        s1 += raw[S3 + idx[i]];
     }
     const int cnt = __builtin_popcount(keep);
     rb[0] = cnt > 0 ? s0 / cnt : rho0[0];
     rb[1] = cnt > 0 ? s1 / cnt : rho0[1];
 }
 
-// =========================================================== k_particle_b
-// One thread per node of the new bounding box.  Uncovered nodes (particle at
-// X^n, fluid at X^{n+1}) get f_eq(rho_bar, u_b) written into the slots they
-// pull from, rho_bar being the mean density of their neighbours fluid at
-// both times; particle nodes at X^{n+1} get the wetting-layer density: mean
-// of their fluid neighbours + / - Delta rho (the mass correction delta is
-// added where it is read).  The last workgroup sums the event partials,
-// computes the global mass correction and publishes the state of step n+1.
+// =============================================================== k_links
+// One thread per node of the box of X^n.  A node p fluid at X^n with links
+// to the sphere (p + c_i a particle node) applies the moving-wall
+// bounce-back f_opp(i)(p) = f*_i(p) - 6 w_i rho_l(p) (c_i . u_b), u_b the
+// rigid velocity at the link midpoint, and writes it into the slot p pulls
+// from (opp(i) at p + c_i) for the next step; it sums the exchanged momentum
+// sum_l (2 f*_i - 6 w_i rho_l c_i . u_b) c_i and its torque about X^n, the
+// bounce-back mass flux and the reaction of the wetting layer on the sphere.
+// Every fluid box node then forms its step-(n+1) populations (plain pulls,
+// its own bounced values on links) and stores their densities and momentum
+// for the particle kernel.  Per-workgroup FP64 sums, fixed order.
 template <typename S, typename T, int B>
-__global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
+__global__ __launch_bounds__(B) void k_links(LinkArgs a) {
+    __shared__ double red[(B / 64) * 16];
+    const int r = find_rep(a.k3_begin, a.nrep, blockIdx.x);
+    const RepDesc D = a.desc[r];  // by value: no reload after stores
+    const RepState st = a.state[r];
+    if (!D.has_particle) return;
+    const Geo g = geo_of(D);
+    const int t = threadIdx.x;
+    const int local = blockIdx.x - D.k3_begin;
+    const int Sx = D.S, S3 = Sx * Sx * Sx;
+    const int32_t org[3] = {st.org[0], st.org[1], st.org[2]};
+    const double X[3] = {st.X[0], st.X[1], st.X[2]};
+    const double *vrho = a.vrho + D.bbox_off * 2;
+    const double *rho_n = a.rho_n + D.bbox_off * 2;
+    double *raw = a.raw + D.bbox_off * RAW;
+    S *buf = reinterpret_cast<S *>(a.buf) + D.pop_off;
+    const PullCtx<S, T> pc = pull_ctx<S, T>(a.buf, D, g);
+    const uint32_t NP = g.NP;
+    double acc[15];
+#pragma unroll
+    for (int k = 0; k < 15; k++) acc[k] = 0.0;
+    const int b = local * B + t;
+    int bb[3], p[3];
+    const bool in = b < S3 && bbox_pos(b, org, Sx, g, bb, p);
+    Nbr nb;
+    nbr_of(p, X, g, nb);
+    const bool fluid = in && !pnode_nb(nb, 0, D.R2);
+    // Loads, arithmetic and stores are kept in three separate phases: on this
+    // architecture loads and stores share one wait counter, so a store issued
+    // before a later load's wait would turn that wait into a write round trip.
+    uint32_t links = 0;
+    uint32_t own = 0;
+    S sv[2][Q];
+    double rw[RAW];
+    if (fluid) {
+        // fluid node: links to neighbours that are particle nodes at X^n
+#pragma unroll
+        for (int i = 1; i < Q; i++)
+            if (box_nb(bb, i, Sx) >= 0 && nbr_ok(nb, i) && pnode_nb(nb, i, D.R2)) links |= 1u << i;
+        // plain pulls, own post-collision values (own slots are always valid,
+        // so they are loaded unconditionally), own densities
+        own = pidx(p[0], p[1], p[2], g);
+        T d[2][Q];
+        pull_node(pc, own, d);
+        T fo[2][Q];
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+#pragma unroll
+            for (int l = 0; l < 2; l++) {
+                const T sc = Rel<S>::value ? T(wgt(i) * D.rho0[l]) : T(1);
+                fo[l][i] = ld_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + own), sc);
+            }
+        }
+        const double rA = rho_n[b], rB = rho_n[S3 + b];
+        if (links) {
+            const double U[3] = {st.U[0], st.U[1], st.U[2]};
+            const double W[3] = {st.W[0], st.W[1], st.W[2]};
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                if (!((links >> i) & 1u)) continue;
+                const double rr[3] = {sepd(p[0] + 0.5 * cx(i) - X[0], g.nx, g.wx),
+                                      sepd(p[1] + 0.5 * cy(i) - X[1], g.ny, g.wy),
+                                      sepd(p[2] + 0.5 * cz(i) - X[2], g.nz, g.wz)};
+                const double ub[3] = {U[0] + W[1] * rr[2] - W[2] * rr[1],
+                                      U[1] + W[2] * rr[0] - W[0] * rr[2],
+                                      U[2] + W[0] * rr[1] - W[1] * rr[0]};
+                const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
+                const double rl[2] = {rA, rB};
+                double mom = 0.0;
+#pragma unroll
+                for (int l = 0; l < 2; l++) {
+                    const double wr = wgt(i) * D.rho0[l];
+                    const double fs = wr + (double)fo[l][i];
+                    const double corr = 6.0 * wgt(i) * rl[l] * cu;
+                    mom += 2.0 * fs - corr;
+                    acc[6 + l] -= corr;
+                    d[l][opp(i)] = store_round<S, T>(fs - corr - wr, T(1.0 / wr), T(wgt(i)) * pc.scale[l], sv[l][i]);
+                }
+                const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
+                acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
+                acc[3] += rr[1] * lp[2] - rr[2] * lp[1];
+                acc[4] += rr[2] * lp[0] - rr[0] * lp[2];
+                acc[5] += rr[0] * lp[1] - rr[1] * lp[0];
+                acc[14] += 1.0;
+            }
+        }
+        // densities and momentum of step n+1 at this node
+        NodeM<T, true> m;
+        node_moments(d, m);
+        rw[0] = D.rho0[0] + (double)m.rd[0];
+        rw[1] = D.rho0[1] + (double)m.rd[1];
+#pragma unroll
+        for (int q = 0; q < 3; q++) rw[2 + q] = (double)m.j[0][q] + (double)m.j[1][q];
+    }
+    if (in && !fluid) {
+        // particle node s: reaction of the wetting layer, i.e. the Shan-Chen
+        // force -G rho_l(x) w_k rho~_l'(s) c on each fluid neighbour x = s + c_k
+        // (link direction c = -c_k), summed here from the particle side
+        const double vA = vrho[b] + st.delta[0], vB = vrho[S3 + b] + st.delta[1];
+        double rn[2][Q];
+        uint32_t fl = 0;
+#pragma unroll
+        for (int k = 1; k < Q; k++) {
+            rn[0][k] = rn[1][k] = 0.0;
+            const int xb = box_nb(bb, k, Sx);
+            if (xb < 0 || !nbr_ok(nb, k) || pnode_nb(nb, k, D.R2)) continue;
+            fl |= 1u << k;
+            rn[0][k] = rho_n[xb];
+            rn[1][k] = rho_n[S3 + xb];
+        }
+#pragma unroll
+        for (int k = 1; k < Q; k++) {
+            if (!((fl >> k) & 1u)) continue;
+            const double rr[3] = {sepd(p[0] + 0.5 * cx(k) - X[0], g.nx, g.wx),
+                                  sepd(p[1] + 0.5 * cy(k) - X[1], g.ny, g.wy),
+                                  sepd(p[2] + 0.5 * cz(k) - X[2], g.nz, g.wz)};
+            const double sw = -D.G * wgt(k) * (rn[0][k] * vB + rn[1][k] * vA);
+            const double f3[3] = {-sw * cx(k), -sw * cy(k), -sw * cz(k)};
+            acc[8] += f3[0]; acc[9] += f3[1]; acc[10] += f3[2];
+            acc[11] += rr[1] * f3[2] - rr[2] * f3[1];
+            acc[12] += rr[2] * f3[0] - rr[0] * f3[2];
+            acc[13] += rr[0] * f3[1] - rr[1] * f3[0];
+        }
+    }
+    if (fluid) {
+        // stores: bounced values into the slots p pulls from at p + c_i (a
+        // ghost when the link crosses a periodic face), then the node's raw
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (!((links >> i) & 1u)) continue;
+            const uint32_t tgt = own + (uint32_t)doff(i, g);
+#pragma unroll
+            for (int l = 0; l < 2; l++) buf[(uint32_t)(l * Q + opp(i)) * NP + tgt] = sv[l][i];
+        }
+#pragma unroll
+        for (int k = 0; k < RAW; k++) raw[k * S3 + b] = rw[k];
+    }
+    block_sum<B, 15>(acc, red);
+    if (t == 0) {
+        double *pp = a.part1 + D.part3_off + (int64_t)local * PART;
+        for (int k = 0; k < 15; k++) pp[k] = acc[k];
+    }
+}
+
+// ============================================================ k_particle
+// One thread per node of the box of X^{n+1}.  Every wave reduces the link
+// sums (fixed order) and advances the sphere: leap-frog Newton-Euler under
+// F = links - wetting reaction + F_ext + pending event momentum.  Each node
+// then takes its flags at X^{n+1} (the FP64 predicate, evaluated here for
+// both positions), and
+//  * covered (fluid at X^n, particle at X^{n+1}): adds its momentum and
+//    mass to the event sums;
+//  * uncovered (particle at X^n, fluid at X^{n+1}): gets f_eq(rho_bar, u_b)
+//    written into the slots it pulls from, rho_bar the mean density of its
+//    neighbours fluid at both times;
+//  * particle node at X^{n+1}: gets the wetting-layer density, mean of its
+//    fluid neighbours +/- Delta rho (the mass correction delta is added
+//    where it is read).
+// The last workgroup sums the event partials, computes the global mass
+// correction and publishes the state of step n+1.
+template <typename S, typename T, int B>
+__global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     __shared__ double red[(B / 64) * 20];
     __shared__ int last;
     const int wg = blockIdx.x;
     const int r = find_rep(a.k3_begin, a.nrep, wg);
-    const RepDesc &D = a.desc[r];
+    const RepDesc D = a.desc[r];  // by value: no reload after stores
     RepState *st = a.state + r;
     const Geo g = geo_of(D);
     const int t = threadIdx.x;
@@ -792,103 +830,160 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
         }
         return;
     }
-    const int32_t org[3] = {st->orgn[0], st->orgn[1], st->orgn[2]};
-    const double Xn[3] = {st->Xn[0], st->Xn[1], st->Xn[2]};
-    const double Un[3] = {st->Un[0], st->Un[1], st->Un[2]};
-    const double Wn[3] = {st->Wn[0], st->Wn[1], st->Wn[2]};
+    double X[3], U[3], Wv[3];
+    int32_t orgo[3];
+    for (int q = 0; q < 3; q++) {
+        X[q] = st->X[q]; U[q] = st->U[q]; Wv[q] = st->W[q]; orgo[q] = st->org[q];
+    }
+    // 1. link momentum exchange and wetting-layer reaction of step n
+    double sum[15];
+    sum_partials<15>(a.part1 + D.part3_off, D.k3_count, 0, sum);
+    // 2. Newton-Euler, leap-frog
+    double F[3], Tq[3], Un[3], Wn[3], Xn[3];
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    const bool w3[3] = {g.wx, g.wy, g.wz};
+    for (int q = 0; q < 3; q++) {
+        F[q] = sum[q] - sum[8 + q] + D.Fext[q] + st->Pev[q];
+        Tq[q] = sum[3 + q] - sum[11 + q] + st->Lev[q];
+        Un[q] = D.fixed_velocity ? U[q] : U[q] + F[q] / D.mp;
+        Wn[q] = D.fixed_velocity ? Wv[q] : Wv[q] + Tq[q] / D.Ip;
+    }
+    int org[3];
+    for (int q = 0; q < 3; q++) {
+        Xn[q] = X[q] + Un[q];
+        if (!w3[q]) {
+            if (Xn[q] >= n3[q]) Xn[q] -= n3[q];
+            else if (Xn[q] < 0.0) Xn[q] += n3[q];
+        }
+        org[q] = (int)floor(Xn[q] - D.radius) - 2;  // box of X^{n+1}
+    }
     const int Sx = D.S, S3 = Sx * Sx * Sx;
-    const double *raw = a.raw + D.bbox_off * 2;
+    const double *raw = a.raw + D.bbox_off * RAW;
     double *vrho = a.vrho + D.bbox_off * 2;
-    const uint8_t *flags = a.flags + D.bbox_off;
+    uint32_t *pmask = a.pmask + D.bbox_off;
     S *buf = reinterpret_cast<S *>(a.buf) + D.pop_off;
     const uint32_t NP = g.NP;
 
-    double unc[10];
-    for (int k = 0; k < 10; k++) unc[k] = 0.0;
+    // 3. events and wetting layer
+    double ev[20];
+#pragma unroll
+    for (int k = 0; k < 20; k++) ev[k] = 0.0;
     const int b = local * B + t;
-    if (b < S3) {
-        const int f = flags[b];
-        int bb[3], p[3];
-        bbox_pos(b, org, Sx, g, bb, p);
-        if ((f & 1) && !(f & 2) && (f & 4)) {  // uncovered
+    int bb[3], p[3];
+    const bool in = b < S3 && bbox_pos(b, org, Sx, g, bb, p);
+    Nbr no, nn;
+    nbr_of(p, X, g, no);
+    nbr_of(p, Xn, g, nn);
+    const bool fo = in && !pnode_nb(no, 0, D.R2);
+    const bool fn = in && !pnode_nb(nn, 0, D.R2);
+    int bo[3];
+    const bool inbox = box_coords(p, orgo, Sx, g, bo);
+    // Loads and arithmetic first, every store last (loads and stores share
+    // one wait counter here).
+    double vw[2] = {0.0, 0.0};
+    if (in && !fn) {  // particle node at X^{n+1} (covered ones included): wetting layer
+        ev[9] += 1.0;
+        int idx[Q];
+        uint32_t kept = 0, fresh = 0;  // fluid at X^{n+1}; of those, uncovered now
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            idx[i] = -1;
+            if (!nbr_ok(nn, i) || pnode_nb(nn, i, D.R2)) continue;
+            if (pnode_nb(no, i, D.R2)) {
+                fresh |= 1u << i;
+            } else {
+                idx[i] = inbox ? box_nb(bo, i, Sx) : -1;
+                if (idx[i] < 0) continue;
+            }
+            kept |= 1u << i;
+        }
+        double r0[Q], r1[Q];
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            r0[i] = r1[i] = 0.0;
+            if (((kept & ~fresh) >> i) & 1u) {
+                r0[i] = raw[idx[i]];
+                r1[i] = raw[S3 + idx[i]];
+            }
+        }
+        // a neighbour uncovered at this step carries its f_eq density (rare)
+        for (uint32_t m = fresh; m; m &= m - 1) {
+            const int i = __builtin_ctz(m);
+            int q[3];
+            nb_pos(p, i, g, q);
             double rb[2];
-            mean_kept_neighbours(bb, Sx, S3, flags, raw, D.rho0, rb);
-            const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
-                                  sepd(p[2] - Xn[2], g.nz, g.wz)};
-            const double u[3] = {Un[0] + Wn[1] * rr[2] - Wn[2] * rr[1],
-                                 Un[1] + Wn[2] * rr[0] - Wn[0] * rr[2],
-                                 Un[2] + Wn[0] * rr[1] - Wn[1] * rr[0]};
-            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            const uint32_t own = pidx(p[0], p[1], p[2], g);
-            for (int i = 0; i < Q; i++) {
-                const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
-                const double e = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-                const uint32_t src = own - (uint32_t)doff(i, g);
-                for (int l = 0; l < 2; l++) {
-                    const double wr = wgt(i) * D.rho0[l];
-                    const double dev = wgt(i) * rb[l] * e - wr;
-                    st_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + src), T(dev),
-                                 Rel<S>::value ? T(1.0 / wr) : T(1));
-                }
-            }
-            const double mom[3] = {(rb[0] + rb[1]) * u[0], (rb[0] + rb[1]) * u[1],
-                                   (rb[0] + rb[1]) * u[2]};
-            unc[0] += mom[0]; unc[1] += mom[1]; unc[2] += mom[2];
-            unc[3] += rr[1] * mom[2] - rr[2] * mom[1];
-            unc[4] += rr[2] * mom[0] - rr[0] * mom[2];
-            unc[5] += rr[0] * mom[1] - rr[1] * mom[0];
-            unc[6] += rb[0];
-            unc[7] += rb[1];
-            unc[9] += 1.0;
-        } else if ((f & 1) && !(f & 4)) {  // particle node at X^{n+1}: wetting layer
-            const int self = b;
-            uint32_t kept = 0, fresh = 0;  // fluid at X^{n+1}; of those, uncovered now
+            mean_kept(q, X, Xn, D.R2, raw, orgo, Sx, S3, g, D.rho0, rb);
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                const int qx = bb[0] + cx(i), qy = bb[1] + cy(i), qz = bb[2] + cz(i);
-                const bool inb = qx >= 0 && qy >= 0 && qz >= 0 && qx < Sx && qy < Sx && qz < Sx;
-                const int fq = flags[inb ? (qz * Sx + qy) * Sx + qx : self];
-                if (inb && (fq & 1) && (fq & 4)) {
-                    kept |= 1u << i;
-                    if (!(fq & 2)) fresh |= 1u << i;
-                }
-            }
-            double r0[Q], r1[Q];
+            for (int k = 1; k < Q; k++)
+                if (k == i) { r0[k] = rb[0]; r1[k] = rb[1]; }
+        }
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                r0[i] = r1[i] = 0.0;
-                if (((kept & ~fresh) >> i) & 1u) {
-                    const int qb = self + (cz(i) * Sx + cy(i)) * Sx + cx(i);
-                    r0[i] = raw[qb];
-                    r1[i] = raw[S3 + qb];
-                }
-            }
-            // a neighbour uncovered at this step carries its f_eq density (rare)
-            for (uint32_t m = fresh; m; m &= m - 1) {
-                const int i = __builtin_ctz(m);
-                const int qq[3] = {bb[0] + cx(i), bb[1] + cy(i), bb[2] + cz(i)};
-                double rb[2];
-                mean_kept_neighbours(qq, Sx, S3, flags, raw, D.rho0, rb);
-#pragma unroll
-                for (int k = 1; k < Q; k++)
-                    if (k == i) { r0[k] = rb[0]; r1[k] = rb[1]; }
-            }
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                if (!((kept >> i) & 1u)) continue;
-                s0 += r0[i];
-                s1 += r1[i];
-            }
-            const int cnt = __builtin_popcount(kept);
-            vrho[b] = cnt > 0 ? s0 / cnt + D.drho : 0.0;
-            vrho[S3 + b] = cnt > 0 ? s1 / cnt - D.drho : 0.0;
+        for (int i = 1; i < Q; i++) {
+            if (!((kept >> i) & 1u)) continue;
+            s0 += r0[i];
+            s1 += r1[i];
+        }
+        const int cnt = __builtin_popcount(kept);
+        vw[0] = cnt > 0 ? s0 / cnt + D.drho : 0.0;
+        vw[1] = cnt > 0 ? s1 / cnt - D.drho : 0.0;
+    }
+    if (fo && !fn && inbox) {  // covered
+        const int ob = (bo[2] * Sx + bo[1]) * Sx + bo[0];
+        const double rho[2] = {raw[ob], raw[S3 + ob]};
+        const double jt[3] = {raw[2 * S3 + ob], raw[3 * S3 + ob], raw[4 * S3 + ob]};
+        const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
+                              sepd(p[2] - Xn[2], g.nz, g.wz)};
+        ev[0] += jt[0]; ev[1] += jt[1]; ev[2] += jt[2];
+        ev[3] += rr[1] * jt[2] - rr[2] * jt[1];
+        ev[4] += rr[2] * jt[0] - rr[0] * jt[2];
+        ev[5] += rr[0] * jt[1] - rr[1] * jt[0];
+        ev[6] += rho[0];
+        ev[7] += rho[1];
+        ev[8] += 1.0;
+    }
+    if (b < S3) {
+        pmask[b] = (in && !fn) ? MASK_SOLID : 0u;
+        if (in && !fn) {
+            vrho[b] = vw[0];
+            vrho[S3 + b] = vw[1];
         }
     }
-    block_sum<B, 10>(unc, red);
+    if (in && !fo && fn) {  // uncovered (rare): its loads, then its stores
+        double rb[2];
+        mean_kept(p, X, Xn, D.R2, raw, orgo, Sx, S3, g, D.rho0, rb);
+        const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
+                              sepd(p[2] - Xn[2], g.nz, g.wz)};
+        const double u[3] = {Un[0] + Wn[1] * rr[2] - Wn[2] * rr[1],
+                             Un[1] + Wn[2] * rr[0] - Wn[0] * rr[2],
+                             Un[2] + Wn[0] * rr[1] - Wn[1] * rr[0]};
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const uint32_t own = pidx(p[0], p[1], p[2], g);
+        for (int i = 0; i < Q; i++) {
+            const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+            const double e = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+            const uint32_t src = own - (uint32_t)doff(i, g);
+            for (int l = 0; l < 2; l++) {
+                const double wr = wgt(i) * D.rho0[l];
+                const double dev = wgt(i) * rb[l] * e - wr;
+                st_dev<S, T>(buf + ((uint32_t)(l * Q + i) * NP + src), T(dev),
+                             Rel<S>::value ? T(1.0 / wr) : T(1));
+            }
+        }
+        const double mom[3] = {(rb[0] + rb[1]) * u[0], (rb[0] + rb[1]) * u[1],
+                               (rb[0] + rb[1]) * u[2]};
+        ev[10] += mom[0]; ev[11] += mom[1]; ev[12] += mom[2];
+        ev[13] += rr[1] * mom[2] - rr[2] * mom[1];
+        ev[14] += rr[2] * mom[0] - rr[0] * mom[2];
+        ev[15] += rr[0] * mom[1] - rr[1] * mom[0];
+        ev[16] += rb[0];
+        ev[17] += rb[1];
+        ev[18] += 1.0;
+    }
+    block_sum<B, 20>(ev, red);
     if (t == 0) {
-        double *p = a.part3b + D.part3_off + (int64_t)local * PART;
-        for (int k = 0; k < 10; k++) p[k] = unc[k];
+        double *pp = a.part3 + D.part3_off + (int64_t)local * PART;
+        for (int k = 0; k < 20; k++) pp[k] = ev[k];
     }
     __threadfence();
     __syncthreads();
@@ -899,43 +994,32 @@ __global__ __launch_bounds__(B) void k_particle_b(ParticleArgs a) {
 
     // ---- last workgroup: event sums (fixed order), mass correction, new state
     double tot[20];
-    for (int k = 0; k < 20; k++) tot[k] = 0.0;
-    for (int w = t; w < D.k3_count; w += B) {
-        const double *pa = a.part3 + D.part3_off + (int64_t)w * PART;
-        const double *pb = a.part3b + D.part3_off + (int64_t)w * PART;
-        for (int k = 0; k < 10; k++) {
-            tot[k] += pa[k];
-            tot[10 + k] += pb[k];
-        }
-    }
-    block_sum<B, 20>(tot, red);
+    sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
     if (t != 0) return;
     const double *utot = tot + 10;
-    const double nf = (double)D.N - tot[8];
+    const double nf = (double)D.N - tot[9];
     const int64_t n = st->step;
     double *s = series + 3 * (n % D.series_cap);
-    const int n3[3] = {g.nx, g.ny, g.nz};
-    const bool w3[3] = {g.wx, g.wy, g.wz};
     bool bad = false;
-    for (int l = 0; l < 2; l++) st->delta[l] = -(st->dMbb[l] - tot[6 + l] + utot[6 + l]) / nf;
+    for (int l = 0; l < 2; l++) st->delta[l] = -(sum[6 + l] - tot[6 + l] + utot[6 + l]) / nf;
     for (int q = 0; q < 3; q++) {
-        st->Xp[q] = st->X[q];
+        st->Xp[q] = X[q];
         st->X[q] = Xn[q];
         st->U[q] = Un[q];
         st->W[q] = Wn[q];
-        st->F[q] = st->Fn[q];
-        st->T[q] = st->Tn[q];
+        st->F[q] = F[q];
+        st->T[q] = Tq[q];
         st->Pev[q] = tot[q] - utot[q];
         st->Lev[q] = tot[3 + q] - utot[3 + q];
         st->org[q] = org[q];
         s[q] = Un[q];
-        if (!(fabs(Un[q]) < 0.5) || !isfinite(st->Fn[q])) bad = true;
+        if (!(fabs(Un[q]) < 0.5) || !isfinite(F[q])) bad = true;
         if (w3[q] && (Xn[q] - D.radius < -0.5 || Xn[q] + D.radius > n3[q] - 0.5)) bad = true;
     }
     st->n_fluid = nf;
-    st->n_cov += (int64_t)tot[9];
-    st->n_unc += (int64_t)utot[9];
-    st->n_links = (int64_t)st->nlinks;
+    st->n_cov += (int64_t)tot[8];
+    st->n_unc += (int64_t)utot[8];
+    st->n_links = (int64_t)sum[14];
     if (bad) st->flags |= FLAG_UNSTABLE;
     st->k3_done = 0;
     st->step = n + 1;
@@ -1072,10 +1156,7 @@ hipError_t launch_links_t(const LinkArgs &a, int grid, hipStream_t s) {
 
 template <typename S, typename T>
 hipError_t launch_particle_t(const ParticleArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_particle_a<S, T, 256>), dim3(grid), dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_particle_b<S, T, 256>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_particle<S, T, 256>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -23,10 +23,10 @@ struct RepDesc {
     int32_t nty, nchunk;     // tiles along y, z-chunks
     int32_t wg_begin;        // first main-kernel workgroup of this replica
     int32_t k3_begin, k3_count;  // particle-kernel workgroups
-    int32_t S;               // edge of the particle bounding box (nodes)
+    int32_t S;               // edge of the particle bounding box (nodes), 2 ceil(R) + 6
     int32_t has_particle;
     int64_t bbox_off;        // element offset of this replica in the bbox arrays (S^3 each)
-    int64_t part3_off;       // double offset of the link and particle partials (16 per workgroup)
+    int64_t part3_off;       // double offset of the link and particle partials (PART per workgroup)
     int64_t series_off;      // double offset of the U series ring (3 per entry)
     int32_t series_cap;
     int32_t cz;              // z-chunk of the main kernel
@@ -52,22 +52,17 @@ struct RepState {
     double n_fluid;
     double pad0;
     int64_t step, n_cov, n_unc, n_links;
-    int32_t org[3];          // origin of the bbox arrays written for step n
+    int32_t org[3];          // origin of the bounding box of X^n
     int32_t pad_org;
     uint32_t flags;          // bit0 unstable
     uint32_t k3_done;        // particle-kernel completion counter
     uint32_t pad1[2];
-    // sphere update of the step in flight (written by the first particle kernel)
-    double Xn[3], Un[3], Wn[3], Fn[3], Tn[3];
-    double dMbb[2];          // bounce-back mass flux of the step
-    double nlinks;
-    int32_t orgn[3];
-    int32_t pad2;
 };
 
 constexpr uint32_t FLAG_UNSTABLE = 1u;
 // Node flag of a bounding-box node for one step: MASK_SOLID = particle node at X^n.
 constexpr uint32_t MASK_SOLID = 1u << 19;
-constexpr int PART = 16;     // doubles per workgroup partial
+constexpr int PART = 24;     // doubles per workgroup partial
+constexpr int RAW = 5;       // doubles per box node: rho_A, rho_B, j (post-streaming, step n+1)
 
 }  // namespace lbm

@@ -64,7 +64,7 @@ def test_workspace_sizes(capi):
     dict(nx=1), dict(nx=300), dict(tau_shear=0.5), dict(kT=-1.0), dict(rho0=(1.0, 0.0)),
     dict(force_mode=3), dict(series_cap=0), dict(walls=9), dict(init_amp=0.2),
     dict(nx=16, ny=16, nz=16, walls=3, radius=7.5),           # sphere touches a wall
-    dict(nx=12, ny=12, nz=12, radius=3.0),                    # periodic box too short for the bbox
+    dict(nx=12, ny=12, nz=12, radius=3.5),                    # periodic box too short for the bbox
     dict(nx=16, ny=16, nz=32, walls=3, radius=3.0, U0=(0.0, 0.0, 0.6)),
 ])
 def test_invalid_parameters_rejected(capi, bad):
