@@ -87,6 +87,28 @@ def cpu_baseline(reps, budget_s=15.0):
                       f"workload in FP64 ({el:.1f} s; init {t_init:.1f} s excluded)"}
 
 
+def copy_calibration(torch, mib, steps, warmup):
+    """Plain device-to-device copy of `mib` MiB: its duration gives a copy
+    ceiling, and under rocprofv3 its FETCH_SIZE / WRITE_SIZE per dispatch give
+    the scale between those counters and bytes actually moved."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(max(warmup, 1)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    moved = 2 * n * 4
+    print(json.dumps({"copy_mib": mib, "ms_per_copy": round(ms, 5), "bytes_moved": moved,
+                      "GB/s": round(moved / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +118,9 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of the step: time a plain device copy of this many MiB "
+                         "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (the hot path is one GPU's share); "
@@ -103,6 +128,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_mib:
+        copy_calibration(torch, args.copy_mib, args.steps, args.warmup)
+        return
     from paper_1909_01092_amd.sim import Simulation
     reps, prec, desc = workload(args.workload)
     stream = torch.cuda.Stream()
