@@ -115,7 +115,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="single")
-    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=0, help="fixed main-kernel z-chunk (skips the autotuner)")
+    ap.add_argument("--block", type=int, default=256, help="main-kernel block with --zchunk")
+    ap.add_argument("--autotune", type=int, default=10,
+                    help="steps per candidate of the launch-shape autotuner (0: library default shape)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -136,7 +139,9 @@ def main():
     stream = torch.cuda.Stream()
     sim = Simulation(reps, precision=prec, device="cuda:0", stream=stream)
     if args.zchunk:
-        sim.set_launch(256, args.zchunk)
+        sim.set_launch(args.block, args.zchunk)
+    elif args.autotune > 0:
+        sim.autotune(steps_per_trial=args.autotune, preserve=False)  # before the warm-up
     block, cz = sim.get_launch()
     if args.graph:
         sim.set_graph(args.graph)
@@ -173,7 +178,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32"}[prec], "data": "synthetic",
         "config": {"workload": desc, "replicas": len(reps), "nodes": nodes, "precision": prec,
-                   "block": block, "zchunk": cz, "graph_steps": args.graph,
+                   "block": block, "zchunk": cz, "autotuned": not args.zchunk and args.autotune > 0,
+                   "graph_steps": args.graph,
                    "unstable": unstable},
         "roofline": roof,
     }

@@ -154,10 +154,25 @@ int lbm_checkpoint_bytes(lbm_ctx *c, size_t *bytes);
 int lbm_checkpoint(lbm_ctx *c, void *dev_dst);
 int lbm_restore(lbm_ctx *c, const void *dev_src);
 
-/* Launch shape of the main kernel: block threads (256) and z-chunk length.
- * Rebuilds the tiling; the physics is unchanged. */
+/* Launch shape of the main kernel: block threads (256, 512 or 1024; at least
+ * the longest x-row) and z-chunk length (>= 1; 0 picks the default: the
+ * longest power-of-two chunk up to 16 that keeps about four waves per SIMD
+ * resident).  Rebuilds the tiling; results do not depend on the shape.
+ * LBM_EINVAL for other blocks or a shape needing more than 64 KiB of LDS. */
 int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk);
 int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk);
+
+/* Autotuner of the main-kernel launch shape.  Every block (256, 512, 1024;
+ * at least the longest x-row) and z-chunk (2 ... 32) whose LDS fits is run
+ * for one untimed step plus steps_per_trial steps timed with HIP events on
+ * the context stream; the shape with the shortest mean main-kernel time is
+ * kept.  The trial steps are real steps of the run (results do not depend on
+ * the shape).  With dev_ckpt non-NULL (a device buffer of
+ * lbm_checkpoint_bytes) the state is checkpointed first and restored after,
+ * leaving the run where it was.  Outputs (may be NULL): chosen block and
+ * z-chunk, its mean main-kernel time in ms.  Synchronises the stream. */
+int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *block_out,
+                 int32_t *zchunk_out, double *best_ms);
 
 /* 0: plain launches; k > 0: lbm_step replays a HIP graph of k steps (k even;
  * needs a non-default stream); leftover steps run as plain launches. */

@@ -23,6 +23,7 @@ thread_local std::string g_init_error;
 
 constexpr size_t ALIGN = 256;
 constexpr int MAIN_BLOCK_MIN = 256;
+constexpr size_t MAIN_LDS_MAX = 64 * 1024;
 constexpr int K3_BLOCK = 256;
 constexpr int INIT_BLOCK = 256;
 
@@ -159,7 +160,7 @@ struct lbm_ctx {
     Layout L;
     std::vector<RepDesc> desc;
     std::vector<int32_t> tables;
-    int block = 256, cz = 8;
+    int block = 256, cz = 8, maxnx = 0;
     int main_grid = 0, k3_grid = 0, init_grid = 0;
     size_t lds = 0;
     int cur = 0;
@@ -235,6 +236,22 @@ void build_tiling(lbm_ctx *c) {
     c->k3_grid = k3;
     c->init_grid = iw;
     c->lds = lds_elems * (c->prec == LBM_FP64 ? 8 : 4);
+}
+
+// Longest z-chunk (a power of two up to 16) that still gives the main
+// kernel about four resident waves per SIMD on 256 CUs; 2 if none does.
+int auto_zchunk(lbm_ctx *c) {
+    const int64_t want = 256 * 16 / (c->block / 64);
+    for (int cz = 16; cz >= 2; cz /= 2) {
+        int64_t wgs = 0;
+        for (int r = 0; r < c->nrep; r++) {
+            const lbm_params &q = c->p[r];
+            const int ty = std::max(1, std::min(q.ny, c->block / q.nx));
+            wgs += (int64_t)((q.ny + ty - 1) / ty) * ((q.nz + cz - 1) / cz);
+        }
+        if (wgs >= want) return cz;
+    }
+    return 2;
 }
 
 int upload_desc(lbm_ctx *c) {
@@ -399,6 +416,8 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
             s.W[a] = D.has_particle ? q.W0[a] : 0.0;
         }
     }
+    for (int r = 0; r < n_replicas; r++) c->maxnx = std::max(c->maxnx, p[r].nx);
+    c->cz = auto_zchunk(c);
     build_tiling(c);
     int rc = upload_desc(c);
     if (rc != LBM_OK) { g_init_error = c->err; delete c; return rc; }
@@ -678,13 +697,67 @@ LBM_API int lbm_restore(lbm_ctx *c, const void *dev_src) {
 
 LBM_API int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk) {
     if (!c) return LBM_EINVAL;
-    if (block != 256) return fail(c, LBM_EINVAL, "block must be 256");
-    if (zchunk < 1) return fail(c, LBM_EINVAL, "zchunk must be >= 1");
+    if (block != 256 && block != 512 && block != 1024)
+        return fail(c, LBM_EINVAL, "block must be 256, 512 or 1024");
+    if (zchunk < 0) return fail(c, LBM_EINVAL, "zchunk must be >= 0 (0: automatic)");
+    if (block < c->maxnx) return fail(c, LBM_EINVAL, "block must hold one x-row of every replica");
     c->block = block;
-    c->cz = zchunk;
+    c->cz = zchunk > 0 ? zchunk : auto_zchunk(c);
     build_tiling(c);
+    if (c->lds > MAIN_LDS_MAX) return fail(c, LBM_EINVAL, "launch shape needs too much LDS");
     drop_graph(c);
     return upload_desc(c);
+}
+
+LBM_API int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *block_out,
+                         int32_t *zchunk_out, double *best_ms) {
+    if (!c) return LBM_EINVAL;
+    if (steps_per_trial < 1) return fail(c, LBM_EINVAL, "steps_per_trial must be >= 1");
+    int rc = LBM_OK;
+    if (dev_ckpt && (rc = lbm_checkpoint(c, dev_ckpt)) != LBM_OK) return rc;
+    const bool timing_was = c->timing;
+    const int graph_was = c->graph_steps;
+    c->graph_steps = 0;
+    int best_b = c->block, best_cz = c->cz;
+    double best = -1.0;
+    const int blocks[3] = {256, 512, 1024};
+    const int chunks[5] = {2, 4, 8, 16, 32};
+    for (int bi = 0; bi < 3 && rc == LBM_OK; bi++) {
+        if (blocks[bi] < c->maxnx) continue;
+        for (int ci = 0; ci < 5 && rc == LBM_OK; ci++) {
+            c->block = blocks[bi];
+            c->cz = chunks[ci];
+            build_tiling(c);
+            if (c->lds > MAIN_LDS_MAX) continue;
+            drop_graph(c);
+            if ((rc = upload_desc(c)) != LBM_OK) break;
+            c->timing = false;
+            if ((rc = enqueue_step(c, false)) != LBM_OK) break;  // first launch of this shape
+            c->timing = true;
+            c->ev_used = 0;
+            for (int k = 0; k < steps_per_trial && rc == LBM_OK; k++) rc = enqueue_step(c, true);
+            if (rc != LBM_OK) break;
+            double ms = 0.0;
+            int64_t n = 0;
+            if ((rc = lbm_timing_read(c, &ms, &n)) != LBM_OK) break;
+            if (best < 0.0 || ms < best) { best = ms; best_b = blocks[bi]; best_cz = chunks[ci]; }
+        }
+    }
+    c->timing = timing_was;
+    c->ev_used = 0;
+    c->graph_steps = graph_was;
+    c->block = best_b;
+    c->cz = best_cz;
+    build_tiling(c);
+    drop_graph(c);
+    const int rc2 = upload_desc(c);
+    if (rc == LBM_OK) rc = rc2;
+    if (dev_ckpt && rc == LBM_OK) rc = lbm_restore(c, dev_ckpt);
+    if (rc != LBM_OK) return rc;
+    if (block_out) *block_out = best_b;
+    if (zchunk_out) *zchunk_out = best_cz;
+    if (best_ms) *best_ms = best;
+    return LBM_OK;
 }
 
 LBM_API int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk) {

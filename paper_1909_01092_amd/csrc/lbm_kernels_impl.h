@@ -393,17 +393,24 @@ void k_main(MainArgs a) {
     const int xm = mirror1(x - 1, nx, g.wx), xp = mirror1(x + 1, nx, g.wx);
     const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == g.ny - 1;
 
-    // plane zp is filled while plane zp - 1 collides
-    for (int zp = z0 - 1; zp <= z1; zp++) {
+    // Plane zp is filled while the plane filled before it collides.  Odd
+    // z-chunks march downwards, so two neighbouring chunks read the halo
+    // planes they share at the same time (both at their start or both at
+    // their end) and the second read hits L2.
+    const int dir = (ch & 1) ? -1 : 1;
+    const int zfirst = dir > 0 ? z0 - 1 : z1;
+    const int nplanes = z1 - z0 + 2;
+    for (int k = 0; k < nplanes; k++) {
         // keep uniform values derived from these roots inside the loop (scalar
         // recomputation is cheaper than spilling hoisted copies)
         asm volatile("" : "+s"(k0), "+s"(k1), "+s"(pcl.NP), "+s"(pcl.PX), "+s"(pcl.PXY));
+        const int zp = zfirst + dir * k;
         const NodeM<T, TAU1> cur = nxt;
         const bool cur_fluid = nxt_fluid;
         fill(zp);
         __syncthreads();
-        if (zp <= z0) continue;
-        const int z = zp - 1;
+        if (k < 2) continue;
+        const int z = zp - dir;
         if (inner && cur_fluid) {
             const uint32_t own = pidx(x, y, z, g);
             const T(&rd)[2] = cur.rd;
@@ -1142,6 +1149,14 @@ hipError_t launch_main_t(const MainArgs &a, int grid, int block, size_t lds, hip
     case 256:
         if (tau1) hipLaunchKernelGGL((k_main<S, T, 256, true>), dim3(grid), dim3(256), lds, s, a);
         else hipLaunchKernelGGL((k_main<S, T, 256, false>), dim3(grid), dim3(256), lds, s, a);
+        break;
+    case 512:
+        if (tau1) hipLaunchKernelGGL((k_main<S, T, 512, true>), dim3(grid), dim3(512), lds, s, a);
+        else hipLaunchKernelGGL((k_main<S, T, 512, false>), dim3(grid), dim3(512), lds, s, a);
+        break;
+    case 1024:
+        if (tau1) hipLaunchKernelGGL((k_main<S, T, 1024, true>), dim3(grid), dim3(1024), lds, s, a);
+        else hipLaunchKernelGGL((k_main<S, T, 1024, false>), dim3(grid), dim3(1024), lds, s, a);
         break;
     default: return hipErrorInvalidValue;
     }

@@ -91,8 +91,25 @@ class Simulation:
     def sync(self):
         self._check(self._lib.lbm_sync(self._ctx))
 
-    def set_launch(self, block: int = 256, zchunk: int = 8):
+    def set_launch(self, block: int = 256, zchunk: int = 0):
+        """Main-kernel launch shape; zchunk 0 picks the default chunk."""
         self._check(self._lib.lbm_set_launch(self._ctx, int(block), int(zchunk)))
+
+    def autotune(self, steps_per_trial: int = 10, preserve: bool = True):
+        """Time every admissible (block, z-chunk) of the main kernel and keep the
+        fastest (lbm_autotune).  preserve=True checkpoints and restores the
+        state so the run is left where it was.  Returns (block, zchunk, ms)."""
+        import torch
+        buf = None
+        if preserve:
+            n = C.c_size_t()
+            self._check(self._lib.lbm_checkpoint_bytes(self._ctx, C.byref(n)))
+            buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        b, z, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self._lib.lbm_autotune(self._ctx, int(steps_per_trial),
+                                           C.c_void_p(buf.data_ptr()) if buf is not None else None,
+                                           C.byref(b), C.byref(z), C.byref(ms)))
+        return b.value, z.value, ms.value
 
     def get_launch(self):
         b, z = C.c_int32(), C.c_int32()

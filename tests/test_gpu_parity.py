@@ -208,13 +208,36 @@ def test_ensemble_of_uneven_replicas(Sim):
         compare(sim, r, 1e-12, rep=k, what=f"ensemble replica {k}")
 
 
-def test_launch_shape_does_not_change_results(Sim):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_launch_shape_does_not_change_results(Sim, prec):
+    """Block sizes 256 / 512 / 1024 and z-chunks with ragged tails and both
+    march directions give the same populations."""
     p = workloads.channel(16, 24, kT=1e-5, radius=3.3, seed=11)
-    a, b = Sim(p, "fp64"), Sim(p, "fp64")
-    a.set_launch(256, 3)
-    b.set_launch(256, 24)
-    a.step(20)
-    b.step(20)
+    shapes = [(256, 3), (256, 24), (512, 5), (1024, 2), (1024, 7)]
+    sims = [Sim(p, prec) for _ in shapes]
+    for s, (blk, cz) in zip(sims, shapes):
+        s.set_launch(blk, cz)
+        assert s.get_launch() == (blk, cz)
+        s.step(20)
+    f0 = sims[0].populations()
+    for s, shape in zip(sims[1:], shapes[1:]):
+        e = rel(s.populations(), f0)
+        print(f"{prec} launch {shape}: rel diff {e:.2e}", flush=True)
+        assert e < 1e-14, shape
+
+
+def test_autotune_keeps_the_run_where_it_was(Sim):
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 1e-4), seed=12)
+    a, b = Sim(p, "fp32"), Sim(p, "fp32")
+    a.step(5)
+    b.step(5)
+    blk, cz, ms = a.autotune(steps_per_trial=2, preserve=True)
+    print(f"autotune: block {blk} zchunk {cz} {ms * 1e3:.1f} us", flush=True)
+    assert blk in (256, 512, 1024) and cz >= 2 and ms > 0
+    assert a.get_launch() == (blk, cz)
+    assert a.particle_state()["step"] == 5
+    a.step(10)
+    b.step(10)
     assert rel(a.populations(), b.populations()) < 1e-14
 
 
