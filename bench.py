@@ -52,15 +52,16 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(name, nbytes_alg):
+def traffic_from_profile(name, block, zchunk):
     """HBM bytes per launch of the main kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
+    counter summary, if it was taken on the current kernel sources in the
+    same launch shape."""
     path = os.path.join(ROOT, "profiles", f"k_main_{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash() or d.get("block") != block or d.get("zchunk") != zchunk:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -117,7 +118,7 @@ def main():
     ap.add_argument("--workload", default="single")
     ap.add_argument("--zchunk", type=int, default=0, help="fixed main-kernel z-chunk (skips the autotuner)")
     ap.add_argument("--block", type=int, default=256, help="main-kernel block with --zchunk")
-    ap.add_argument("--autotune", type=int, default=10,
+    ap.add_argument("--autotune", type=int, default=20,
                     help="steps per candidate of the launch-shape autotuner (0: library default shape)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -169,7 +170,7 @@ def main():
         achieved = step_bytes / (kern_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(args.workload, step_bytes),
+                "traffic": traffic_from_profile(args.workload, block, cz),
                 "kernel": "k_main", "kernel_ms": round(kern_ms, 5), "launches": nlaunch,
                 "bytes_per_launch": step_bytes}
     out = {

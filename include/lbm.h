@@ -165,8 +165,8 @@ int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk);
 /* Autotuner of the main-kernel launch shape.  Every block (256, 512, 1024;
  * at least the longest x-row) and z-chunk (2 ... 32) whose LDS fits is run
  * for one untimed step plus steps_per_trial steps timed with HIP events on
- * the context stream; the shape with the shortest mean main-kernel time is
- * kept.  The trial steps are real steps of the run (results do not depend on
+ * the context stream; the three fastest are timed once more, and the shape
+ * with the shortest mean main-kernel time is kept.  The trial steps are real steps of the run (results do not depend on
  * the shape).  With dev_ckpt non-NULL (a device buffer of
  * lbm_checkpoint_bytes) the state is checkpointed first and restored after,
  * leaving the run where it was.  Outputs (may be NULL): chosen block and

@@ -718,31 +718,46 @@ LBM_API int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, in
     const bool timing_was = c->timing;
     const int graph_was = c->graph_steps;
     c->graph_steps = 0;
-    int best_b = c->block, best_cz = c->cz;
-    double best = -1.0;
+    // mean main-kernel time of one shape over steps_per_trial timed steps
+    auto trial = [&](int blk, int cz, double &ms) -> int {
+        c->block = blk;
+        c->cz = cz;
+        build_tiling(c);
+        if (c->lds > MAIN_LDS_MAX) { ms = -1.0; return LBM_OK; }
+        drop_graph(c);
+        int r = upload_desc(c);
+        if (r != LBM_OK) return r;
+        c->timing = false;
+        if ((r = enqueue_step(c, false)) != LBM_OK) return r;  // first launch of this shape
+        c->timing = true;
+        c->ev_used = 0;
+        for (int k = 0; k < steps_per_trial && r == LBM_OK; k++) r = enqueue_step(c, true);
+        if (r != LBM_OK) return r;
+        int64_t n = 0;
+        return lbm_timing_read(c, &ms, &n);
+    };
+    struct Cand { int blk, cz; double ms; };
+    std::vector<Cand> cands;
     const int blocks[3] = {256, 512, 1024};
     const int chunks[5] = {2, 4, 8, 16, 32};
     for (int bi = 0; bi < 3 && rc == LBM_OK; bi++) {
         if (blocks[bi] < c->maxnx) continue;
         for (int ci = 0; ci < 5 && rc == LBM_OK; ci++) {
-            c->block = blocks[bi];
-            c->cz = chunks[ci];
-            build_tiling(c);
-            if (c->lds > MAIN_LDS_MAX) continue;
-            drop_graph(c);
-            if ((rc = upload_desc(c)) != LBM_OK) break;
-            c->timing = false;
-            if ((rc = enqueue_step(c, false)) != LBM_OK) break;  // first launch of this shape
-            c->timing = true;
-            c->ev_used = 0;
-            for (int k = 0; k < steps_per_trial && rc == LBM_OK; k++) rc = enqueue_step(c, true);
-            if (rc != LBM_OK) break;
-            double ms = 0.0;
-            int64_t n = 0;
-            if ((rc = lbm_timing_read(c, &ms, &n)) != LBM_OK) break;
-            if (best < 0.0 || ms < best) { best = ms; best_b = blocks[bi]; best_cz = chunks[ci]; }
+            double ms = -1.0;
+            rc = trial(blocks[bi], chunks[ci], ms);
+            if (rc == LBM_OK && ms > 0.0) cands.push_back({blocks[bi], chunks[ci], ms});
         }
     }
+    // the three fastest are timed again; each keeps the better of its two means
+    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    for (size_t k = 0; k < cands.size() && k < 3 && rc == LBM_OK; k++) {
+        double ms = -1.0;
+        rc = trial(cands[k].blk, cands[k].cz, ms);
+        if (rc == LBM_OK && ms > 0.0) cands[k].ms = std::min(cands[k].ms, ms);
+    }
+    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+    int best_b = cands.empty() ? 256 : cands[0].blk, best_cz = cands.empty() ? auto_zchunk(c) : cands[0].cz;
+    const double best = cands.empty() ? -1.0 : cands[0].ms;
     c->timing = timing_was;
     c->ev_used = 0;
     c->graph_steps = graph_was;

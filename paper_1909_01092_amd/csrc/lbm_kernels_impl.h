@@ -479,12 +479,12 @@ void k_main(MainArgs a) {
                     relax_component(r0l, sig, rdl, jl, ml, Fl, u, xid, zl, cf, out);
                 }
                 const T sc = Rel<S>::value ? r0l : T(1);
-                S *dl_base = dst + l * Q * (int32_t)NP;
+                S *dl_base = dst + l * Q * pcl.NP;
                 const uint32_t own4 = own * (uint32_t)sizeof(S);
 #pragma unroll
                 for (int i = 0; i < Q; i++) {
                     const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
-                    S *col = dl_base + i * (int32_t)NP;
+                    S *col = dl_base + i * pcl.NP;
                     st_dev<S, T>(&at(col, own4), out[i], inv);
                     if (i == 0) continue;
                     // a link that leaves the box also writes its value where the
@@ -498,8 +498,8 @@ void k_main(MainArgs a) {
                         // never negative (x + c_i lies in the ghost layer, the
                         // periodic image x - n c_i inside the box)
                         const bool bounce = (ex && g.wx) || (ey && g.wy) || (ez && g.wz);
-                        const int32_t so = bounce ? opp(i) * (int32_t)NP + doff(i, g)
-                                                  : i * (int32_t)NP + (ex ? -cx(i) * nx : 0) +
+                        const int32_t so = bounce ? opp(i) * pcl.NP + pcl.PX * cy(i) + pcl.PXY * cz(i) + cx(i)
+                                                  : i * pcl.NP + (ex ? -cx(i) * nx : 0) +
                                                         (ey ? -cy(i) * g.ny * g.PX : 0) +
                                                         (ez ? -cz(i) * g.nz * g.PX * g.PY : 0);
                         const uint32_t e = (uint32_t)((int32_t)own + so);
@@ -709,19 +709,20 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
         }
         const double rA = rho_n[b], rB = rho_n[S3 + b];
         if (links) {
-            const double U[3] = {st.U[0], st.U[1], st.U[2]};
-            const double W[3] = {st.W[0], st.W[1], st.W[2]};
+            // rigid velocity at the link midpoint p + c_i/2: c_i . u_b = c_i . (U + W x d)
+            // with d = p - X, since c_i . (W x c_i) = 0; the torque of the summed
+            // link momentum P about X is d x P for the same reason
+            const double dd[3] = {sepd(p[0] - X[0], g.nx, g.wx), sepd(p[1] - X[1], g.ny, g.wy),
+                                  sepd(p[2] - X[2], g.nz, g.wz)};
+            const double V[3] = {st.U[0] + st.W[1] * dd[2] - st.W[2] * dd[1],
+                                 st.U[1] + st.W[2] * dd[0] - st.W[0] * dd[2],
+                                 st.U[2] + st.W[0] * dd[1] - st.W[1] * dd[0]};
+            const double rl[2] = {rA, rB};
+            double P[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 if (!((links >> i) & 1u)) continue;
-                const double rr[3] = {sepd(p[0] + 0.5 * cx(i) - X[0], g.nx, g.wx),
-                                      sepd(p[1] + 0.5 * cy(i) - X[1], g.ny, g.wy),
-                                      sepd(p[2] + 0.5 * cz(i) - X[2], g.nz, g.wz)};
-                const double ub[3] = {U[0] + W[1] * rr[2] - W[2] * rr[1],
-                                      U[1] + W[2] * rr[0] - W[0] * rr[2],
-                                      U[2] + W[0] * rr[1] - W[1] * rr[0]};
-                const double cu = cx(i) * ub[0] + cy(i) * ub[1] + cz(i) * ub[2];
-                const double rl[2] = {rA, rB};
+                const double cu = cx(i) * V[0] + cy(i) * V[1] + cz(i) * V[2];
                 double mom = 0.0;
 #pragma unroll
                 for (int l = 0; l < 2; l++) {
@@ -732,13 +733,15 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
                     acc[6 + l] -= corr;
                     d[l][opp(i)] = store_round<S, T>(fs - corr - wr, T(1.0 / wr), T(wgt(i)) * pc.scale[l], sv[l][i]);
                 }
-                const double lp[3] = {mom * cx(i), mom * cy(i), mom * cz(i)};
-                acc[0] += lp[0]; acc[1] += lp[1]; acc[2] += lp[2];
-                acc[3] += rr[1] * lp[2] - rr[2] * lp[1];
-                acc[4] += rr[2] * lp[0] - rr[0] * lp[2];
-                acc[5] += rr[0] * lp[1] - rr[1] * lp[0];
+                if (cx(i)) P[0] += cx(i) > 0 ? mom : -mom;
+                if (cy(i)) P[1] += cy(i) > 0 ? mom : -mom;
+                if (cz(i)) P[2] += cz(i) > 0 ? mom : -mom;
                 acc[14] += 1.0;
             }
+            acc[0] += P[0]; acc[1] += P[1]; acc[2] += P[2];
+            acc[3] += dd[1] * P[2] - dd[2] * P[1];
+            acc[4] += dd[2] * P[0] - dd[0] * P[2];
+            acc[5] += dd[0] * P[1] - dd[1] * P[0];
         }
         // densities and momentum of step n+1 at this node
         NodeM<T, true> m;
@@ -764,19 +767,23 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
             rn[0][k] = rho_n[xb];
             rn[1][k] = rho_n[S3 + xb];
         }
+        // force on the fluid neighbour x = s + c_k is -sw c_k; its torque about X
+        // is (d_s + c_k/2) x (-sw c_k) = d_s x (-sw c_k), d_s = s - X
+        double Fw[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 1; k < Q; k++) {
             if (!((fl >> k) & 1u)) continue;
-            const double rr[3] = {sepd(p[0] + 0.5 * cx(k) - X[0], g.nx, g.wx),
-                                  sepd(p[1] + 0.5 * cy(k) - X[1], g.ny, g.wy),
-                                  sepd(p[2] + 0.5 * cz(k) - X[2], g.nz, g.wz)};
             const double sw = -D.G * wgt(k) * (rn[0][k] * vB + rn[1][k] * vA);
-            const double f3[3] = {-sw * cx(k), -sw * cy(k), -sw * cz(k)};
-            acc[8] += f3[0]; acc[9] += f3[1]; acc[10] += f3[2];
-            acc[11] += rr[1] * f3[2] - rr[2] * f3[1];
-            acc[12] += rr[2] * f3[0] - rr[0] * f3[2];
-            acc[13] += rr[0] * f3[1] - rr[1] * f3[0];
+            if (cx(k)) Fw[0] += cx(k) > 0 ? -sw : sw;
+            if (cy(k)) Fw[1] += cy(k) > 0 ? -sw : sw;
+            if (cz(k)) Fw[2] += cz(k) > 0 ? -sw : sw;
         }
+        const double ds[3] = {sepd(p[0] - X[0], g.nx, g.wx), sepd(p[1] - X[1], g.ny, g.wy),
+                              sepd(p[2] - X[2], g.nz, g.wz)};
+        acc[8] += Fw[0]; acc[9] += Fw[1]; acc[10] += Fw[2];
+        acc[11] += ds[1] * Fw[2] - ds[2] * Fw[1];
+        acc[12] += ds[2] * Fw[0] - ds[0] * Fw[2];
+        acc[13] += ds[0] * Fw[1] - ds[1] * Fw[0];
     }
     if (fluid) {
         // stores: bounced values into the slots p pulls from at p + c_i (a
