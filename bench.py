@@ -88,6 +88,29 @@ def cpu_baseline(reps, budget_s=15.0):
                       f"workload in FP64 ({el:.1f} s; init {t_init:.1f} s excluded)"}
 
 
+def langevin_stats(sim, reps, steps, skip):
+    """Per-replica mean and variance of the particle velocity U_z over the
+    last steps - skip recorded steps, grouped by lattice size, with the
+    variance in units of kT / m_p (the Langevin prediction, Sec. 3)."""
+    import math
+    import numpy as np
+    groups = {}
+    for r, q in enumerate(reps):
+        if q["radius"] <= 0 or q["series_cap"] < steps:
+            continue
+        u = sim.u_series(r)[-(steps - skip):, 2]
+        mp = 4.0 / 3.0 * math.pi * q["radius"] ** 3 * q["rho_p"]
+        key = f"{q['nx']}x{q['ny']}x{q['nz']},R={q['radius']:g},kT={q['kT']:g}"
+        groups.setdefault(key, []).append((u.mean(), u.var() / (q["kT"] / mp) if q["kT"] > 0 else float("nan")))
+    out = {}
+    for key, v in groups.items():
+        a = np.array(v)
+        out[key] = {"replicas": len(v), "steps_used": steps - skip, "mean_Uz": float(a[:, 0].mean()),
+                    "var_Uz_over_kT_mp": float(a[:, 1].mean()),
+                    "sem": float(a[:, 1].std() / math.sqrt(len(v)))}
+    return out
+
+
 def copy_calibration(torch, mib, steps, warmup):
     """Plain device-to-device copy of `mib` MiB: its duration gives a copy
     ceiling, and under rocprofv3 its FETCH_SIZE / WRITE_SIZE per dispatch give
@@ -122,6 +145,9 @@ def main():
                     help="steps per candidate of the launch-shape autotuner (0: library default shape)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--stats", type=int, default=-1, metavar="SKIP",
+                    help="add per-replica particle-velocity statistics over the timed steps after "
+                         "the first SKIP (needs series_cap >= steps)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the step: time a plain device copy of this many MiB "
                          "(calibrates the HBM byte counters)")
@@ -161,6 +187,7 @@ def main():
     kern_ms, nlaunch = sim.timing_read() if timed else (None, 0)
     sim.timing(False)
 
+    stats = langevin_stats(sim, reps, args.steps, args.stats) if args.stats >= 0 else None
     state = [sim.particle_state(r, allow_unstable=True) for r in range(len(reps))]
     unstable = any(s["unstable"] for s in state)
     mlups = nodes * args.steps / el / 1e6
@@ -184,6 +211,8 @@ def main():
                    "unstable": unstable},
         "roofline": roof,
     }
+    if stats is not None:
+        out["langevin"] = stats
     sim.close()
     del sim
     if not args.no_cpu:

@@ -1,0 +1,77 @@
+"""Statistics of the particle velocity over an ensemble of noise replicas,
+against the Langevin picture the paper verifies (Sec. 3, Langevin section):
+in the steady state Var(U) = kT / m_p whatever kT, the standardized
+velocity is Gaussian, and the mean settling velocity does not depend on kT.  These run the HIP path only; the expected values are the
+closed forms, not the oracle.
+
+Tolerances: 32 replicas x 2000 steady-state steps give a standard error of
+about 2% on the ensemble-mean variance.  The lattice sphere's velocity
+variance is measured at 1.05-1.07 x kT/m_p (64 replicas, 3000 steps), so the
+bound is [0.95, 1.20].
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1909_01092_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+N, NZ, R, STEPS, SKIP = 32, 128, 4.0, 3000, 1000
+
+
+@pytest.fixture(scope="module")
+def series():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_01092_amd.sim import Simulation
+    reps = []
+    for k in range(32):      # two noise levels in one launch
+        kT = 1e-5 if k < 16 else 1e-4
+        reps.append(workloads.channel(N, NZ, kT=kT, radius=R, g=(0, 0, 5e-5), seed=21, replica=k,
+                                      series_cap=STEPS))
+    sim = Simulation(reps, "fp32", stream=torch.cuda.Stream())
+    sim.step(STEPS)
+    U = np.stack([sim.u_series(r) for r in range(len(reps))])
+    assert U.shape == (32, STEPS, 3)
+    assert not any(sim.particle_state(r)["unstable"] for r in range(len(reps)))
+    sim.close()
+    return U[:, SKIP:, :]
+
+
+def m_p():
+    return 4.0 / 3.0 * math.pi * R ** 3 * 2.0
+
+
+@pytest.mark.parametrize("group,kT", [(slice(0, 16), 1e-5), (slice(16, 32), 1e-4)])
+def test_velocity_variance_equals_kT_over_mass(series, group, kT):
+    U = series[group]
+    for a in range(3):
+        ratio = U[:, :, a].var(axis=1).mean() / (kT / m_p())
+        print(f"kT {kT:g} axis {a}: Var(U)/(kT/m_p) = {ratio:.3f}", flush=True)
+        assert 0.95 < ratio < 1.20, (kT, a, ratio)
+
+
+def test_mean_settling_velocity_independent_of_kT(series):
+    """The two noise levels settle at the same mean velocity, within four
+    standard errors of the difference (from the spread of the replicas' own
+    time averages, which already contains the velocity's autocorrelation)."""
+    m_lo, m_hi = series[:16, :, 2].mean(axis=1), series[16:, :, 2].mean(axis=1)
+    lo, hi = m_lo.mean(), m_hi.mean()
+    se = math.sqrt(m_lo.var(ddof=1) / m_lo.size + m_hi.var(ddof=1) / m_hi.size)
+    print(f"<U_z>: kT=1e-5 {lo:.4e}, kT=1e-4 {hi:.4e}, standard error of the difference {se:.2e}",
+          flush=True)
+    assert lo > 0 and hi > 0
+    assert abs(hi - lo) < 4.0 * se
+    assert se < 0.1 * lo
+
+
+def test_standardized_velocity_is_gaussian(series):
+    U = series[16:, :, 2]
+    x = (U - U.mean(axis=1, keepdims=True)) / U.std(axis=1, keepdims=True)
+    x = x.ravel()
+    skew, kurt = float((x ** 3).mean()), float((x ** 4).mean())
+    print(f"standardized U_z: skewness {skew:.3f}, kurtosis {kurt:.3f}", flush=True)
+    assert abs(skew) < 0.1 and abs(kurt - 3.0) < 0.3
