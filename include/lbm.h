@@ -178,15 +178,26 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *b
  * needs a non-default stream); leftover steps run as plain launches. */
 int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph);
 
+/* Overlapped steps (default off; needs a sphere in some replica and a
+ * non-default context stream, otherwise the call keeps them off): the main
+ * kernel runs as two launches of the same kernel, the tiles within one node
+ * of a sphere's bounding box on the context stream, followed there by the
+ * link and particle kernels, and all other tiles on a second library-owned
+ * stream at the same time; the two streams join at the end of every step.
+ * Results are identical either way.  Synchronises the context stream. */
+int lbm_set_overlap(lbm_ctx *c, int32_t enable);
+
 /* Timing of the main kernel: while enabled, every plain-launch step records
- * HIP events around the main kernel on the context stream.
- * lbm_timing_read returns the mean duration (ms) and the number of timed
- * launches since it was enabled. */
+ * HIP events around the main-kernel launch (its far-tile part when steps are
+ * overlapped) on the stream it runs on.  lbm_timing_read returns the mean
+ * duration (ms) and the number of timed launches since it was enabled. */
 int lbm_timing(lbm_ctx *c, int32_t enable);
 int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count);
 
-/* Algorithmic bytes one step of the main kernel moves (read + write of
- * 2 x 19 populations per node, all replicas). */
+/* Algorithmic bytes the timed main-kernel launch moves per step (read +
+ * write of 2 x 19 populations per node it updates: every node, or the nodes
+ * of the far tiles for the current sphere positions when overlapped).
+ * Synchronises the context stream. */
 int lbm_step_bytes(lbm_ctx *c, double *bytes);
 
 void lbm_destroy(lbm_ctx *c);

@@ -157,6 +157,11 @@ struct lbm_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
+    // split steps: the main kernel's tiles far from the sphere run on stream2
+    // while the near tiles, link and particle kernels run on stream
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool split = false;
     Layout L;
     std::vector<RepDesc> desc;
     std::vector<int32_t> tables;
@@ -281,21 +286,32 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     m.vrho = c->d_vrho();
     m.rho_n = c->d_rho_n();
     m.tau1 = c->tau1;
-    if (timed) {
-        if (c->ev_used + 2 > c->ev.size()) {
-            for (int k = 0; k < 256; k++) {
-                hipEvent_t e;
-                HIP_TRY(c, hipEventCreate(&e));
-                c->ev.push_back(e);
-            }
+    if (timed && c->ev_used + 2 > c->ev.size()) {
+        for (int k = 0; k < 256; k++) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            c->ev.push_back(e);
         }
-        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
     }
-    hipError_t e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, c->stream);
+    // the timed launch: the whole main kernel, or its far part when split
+    hipStream_t ts = c->split ? c->stream2 : c->stream;
+    if (c->split) {
+        HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    }
+    if (timed) HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], ts));
+    m.part = c->split ? 2 : 0;
+    hipError_t e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, ts);
     if (e != hipSuccess) return hip_fail(c, e, "main kernel launch");
     if (timed) {
-        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], ts));
         c->ev_used += 2;
+    }
+    if (c->split) {
+        HIP_TRY(c, hipEventRecord(c->ev_join, c->stream2));
+        m.part = 1;
+        e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "main kernel launch (near part)");
     }
     LinkArgs la;
     la.desc = c->d_desc();
@@ -323,8 +339,41 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     pa.series = c->d_series();
     e = launch_particle(c->prec, pa, c->k3_grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "particle kernel launch");
+    if (c->split) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur = 1 - c->cur;
     return LBM_OK;
+}
+
+// Split steps need a sphere in some replica and a non-default caller stream.
+int set_split(lbm_ctx *c, bool on) {
+    bool any = false;
+    for (const RepDesc &D : c->desc) any = any || D.has_particle;
+    on = on && any && c->stream != nullptr;
+    if (on && !c->stream2) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    if (on != c->split) drop_graph(c);
+    c->split = on;
+    return LBM_OK;
+}
+
+// nodes updated by the timed main-kernel launch: all of them, or those in
+// tiles far from the spheres' boxes of the current state
+int64_t timed_nodes(lbm_ctx *c, const std::vector<RepState> &st) {
+    int64_t n = 0;
+    for (int r = 0; r < c->nrep; r++) {
+        const RepDesc &D = c->desc[r];
+        for (int ch = 0; ch < D.nchunk; ch++)
+            for (int yt = 0; yt < D.nty; yt++) {
+                const int y0 = yt * D.ty, y1 = std::min(y0 + D.ty, D.ny);
+                const int z0 = ch * D.cz, z1 = std::min(z0 + D.cz, D.nz);
+                if (c->split && tile_near_box(D, st[r].org, y0, y1, z0, z1)) continue;
+                n += (int64_t)D.nx * (y1 - y0) * (z1 - z0);
+            }
+    }
+    return n;
 }
 
 int check_rep(lbm_ctx *c, int r) {
@@ -815,13 +864,29 @@ LBM_API int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count) {
 
 LBM_API int lbm_step_bytes(lbm_ctx *c, double *bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    *bytes = 2.0 * 38.0 * (double)c->L.Ntot * (double)c->es;
+    std::vector<RepState> st(c->nrep);
+    HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_state(), sizeof(RepState) * c->nrep, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *bytes = 2.0 * 38.0 * (double)timed_nodes(c, st) * (double)c->es;
     return LBM_OK;
+}
+
+LBM_API int lbm_set_overlap(lbm_ctx *c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return set_split(c, enable != 0);
 }
 
 LBM_API void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     drop_graph(c);
+    if (c->stream2) {
+        hipStreamSynchronize(c->stream2);
+        hipStreamDestroy(c->stream2);
+    }
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
 }
