@@ -240,6 +240,14 @@ def test_wetting_layer_force_closed_form(oracle_lib):
     assert checked > 50
 
 
+def _paper(key):
+    """A value the paper prints (tests/golden/paper_sec2_parameters.json, with its place)."""
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_sec2_parameters.json")
+    with open(path) as fh:
+        return json.load(fh)[key]["value"]
+
+
 def _decay_rate(series, t0, t1):
     return -np.log(series[t1] / series[t0]) / (t1 - t0)
 
@@ -251,7 +259,7 @@ def test_shear_viscosity(oracle_lib, tau):
     e, w, b, c = oracle_lib.basis()
     cf = c.astype(float)
     nx, A = 32, 1e-4
-    rA, rB = 2.21, 0.09
+    rA, rB = _paper("rho_A"), _paper("rho_B")
     sim = oracle_lib.OracleSim(dict(nx=nx, ny=2, nz=2, rho0=(rA, rB), tau_shear=tau))
     k = 2 * np.pi / nx
     f = np.zeros((2, Q, 2, 2, nx))
@@ -268,7 +276,7 @@ def test_shear_viscosity(oracle_lib, tau):
     nu = _decay_rate(np.array(amp), 20, 120) / k**2
     assert nu == pytest.approx((tau - 0.5) / 3.0, rel=0.01)
     if tau == 1.0:
-        assert (rA + rB) * nu == pytest.approx(0.383, abs=6e-4)
+        assert (rA + rB) * nu == pytest.approx(_paper("eta"), abs=6e-4)
 
 
 def test_interdiffusion_coefficient(oracle_lib):
@@ -290,7 +298,7 @@ def test_interdiffusion_coefficient(oracle_lib):
         amp.append(2.0 / nx * np.sum((rho[0, 0, 0] - 0.5) * np.sin(k * np.arange(nx))))
         sim.step(1)
     D = _decay_rate(np.array(amp), 20, 120) / k**2
-    assert D == pytest.approx(1.0 / 6.0, rel=0.01)
+    assert D == pytest.approx(_paper("D"), rel=0.01)
 
 
 def _block_se(x, nblocks=25):
