@@ -240,14 +240,36 @@ __device__ __forceinline__ void node_moments(const T (&d)[2][Q], NodeM<T, TAU1> 
 }
 
 // ------------------------------------------------------- block reductions
+// x + (x moved across lanes by the DPP pattern CTRL), FP64 as two 32-bit moves
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const int plo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+    const int phi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+    return x + __hiloint2double(phi, plo);
+}
+
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum over the 64 lanes of a wave, in a fixed order and bitwise the same in
+// every lane: lane pairs, then quads, 8-lane halves and 16-lane rows are
+// combined with DPP permutations (quad swaps, half-row and row mirrors; each
+// step adds two equal partial sums in either order, so all lanes agree), and
+// the four row sums are read from lanes 0, 16, 32, 48 and added in order.
+// All lanes of the wave must be active.
 template <int NV>
 __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; k++) {
         double x = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        v[k] = x;
+        x = dpp_add<0xB1>(x);   // quad_perm [1,0,3,2]
+        x = dpp_add<0x4E>(x);   // quad_perm [2,3,0,1]
+        x = dpp_add<0x141>(x);  // row_half_mirror
+        x = dpp_add<0x140>(x);  // row_mirror
+        v[k] = ((lane_value(x, 0) + lane_value(x, 16)) + lane_value(x, 32)) + lane_value(x, 48);
     }
 }
 
@@ -256,21 +278,16 @@ template <int B, int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *red /* [B/64][NV] */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     wave_sum<NV>(v);
-    __syncthreads();
+    __syncthreads();  // earlier readers of red are done
     if (lane == 0)
         for (int k = 0; k < NV; k++) red[wave * NV + k] = v[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < NV; k++) {
-            double s = 0.0;
-            for (int w = 0; w < B / 64; w++) s += red[w * NV + k];
-            red[k] = s;
-        }
-    }
-    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; k++) v[k] = red[k];
-    __syncthreads();
+    for (int k = 0; k < NV; k++) {
+        double s = 0.0;
+        for (int w = 0; w < B / 64; w++) s += red[w * NV + k];
+        v[k] = s;
+    }
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin; give each XCD a
