@@ -307,11 +307,13 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
 // current plane collides.  The sphere enters only through the solid flags
 // and wetting-layer densities of its bounding box; every FP64 particle
 // computation lives in the bounding-box kernels.
-// FP32 storage with all relaxation times 1: both components unrolled and the
-// kernel held to 128 VGPRs (four waves per SIMD).  Other forms keep the
-// component loop rolled and their natural register allocation.
+// FP32 arithmetic with all relaxation times 1 (FP32 or FP16 storage): both
+// components unrolled and the kernel held to 128 VGPRs (four waves per SIMD).
+// Other forms keep the component loop rolled and their natural allocation.
 template <typename S, typename T, bool TAU1>
-constexpr bool main_fast_form = sizeof(S) == 4 && sizeof(T) == 4 && TAU1;
+constexpr bool main_fast_form = sizeof(T) == 4 && TAU1;
+template <typename S, typename T, bool TAU1>
+constexpr bool main_unroll = sizeof(T) == 4 && TAU1;
 
 template <typename S, typename T, int B, bool TAU1>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(main_fast_form<S, T, TAU1> ? 4 : 1)))
@@ -472,7 +474,7 @@ void k_main(MainArgs a) {
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
             const bool zlo = z == 0, zhi = z == g.nz - 1;
-            constexpr int kCompUnroll = main_fast_form<S, T, TAU1> ? 2 : 1;
+            constexpr int kCompUnroll = main_unroll<S, T, TAU1> ? 2 : 1;
 #pragma unroll kCompUnroll
             for (int l = 0; l < 2; l++) {
                 // this component's values (selected, so nothing is indexed by l)
