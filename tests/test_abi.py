@@ -102,3 +102,13 @@ def test_lattice_size_limit_depends_on_precision(capi):
     assert e.value.code == capi.LBM_EINVAL and b"too large" in str(e.value).encode()
     with pytest.raises(capi.LbmError):
         workspace_bytes(dict(nx=200, ny=200, nz=1500, walls=3), "fp32")
+
+
+def test_empty_replica_list_rejected(capi):
+    from paper_1909_01092_amd.sim import make_params
+    arr = make_params(dict(nx=16, ny=16, nz=16))
+    n = C.c_size_t()
+    L = capi.lib()
+    assert L.lbm_workspace_bytes(arr, 0, 1, C.byref(n)) == capi.LBM_EINVAL
+    assert L.lbm_workspace_bytes(arr, -3, 1, C.byref(n)) == capi.LBM_EINVAL
+    assert b"n_replicas" in L.lbm_last_error(None)

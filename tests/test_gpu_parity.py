@@ -283,3 +283,38 @@ def test_overlapped_steps_equal_serial_steps(Sim, prec):
             ref = OracleSim(p)
             ref.step(37)
             compare(a, ref, 1e-12, what="overlapped steps vs oracle")
+
+
+@pytest.mark.parametrize("case", ["smallest", "widest_row", "no_noise", "sphere_without_nodes"])
+def test_degenerate_and_extreme_shapes_fp64(Sim, case):
+    """The smallest lattice (2 x 2 x 2, periodic), an x-row at the 256-node
+    maximum (one row per workgroup), kT = 0 (no noise), and a sphere too
+    small to cover any node (only its external force acts)."""
+    if case == "smallest":
+        p = workloads.full(dict(nx=2, ny=2, nz=2, walls=0, G=1.5, kT=1e-4, init_amp=1e-3, seed=3))
+    elif case == "widest_row":
+        p = workloads.full(dict(nx=256, ny=3, nz=4, walls=3, G=1.5, kT=1e-5, init_amp=1e-3,
+                                g=(0.0, 0.0, 1e-5), force_mode=1, seed=3))
+    elif case == "no_noise":
+        p = workloads.channel(16, 24, kT=0.0, radius=3.3, g=(0, 0, 1e-4), seed=3)
+    else:
+        p = workloads.channel(12, 20, kT=1e-5, radius=0.3, g=(0, 0, 1e-4), seed=3)
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.step(12)
+    ref.step(12)
+    compare(sim, ref, 1e-12, what=f"{case} after 12 steps")
+    if p["radius"] > 0:
+        compare_particle(sim, ref, 1e-9, what=case)
+
+
+def test_instability_is_reported(Sim):
+    """A driving force that pushes the sphere past |U| = 1/2 sets the sticky
+    unstable flag; the state query then returns LBM_EUNSTABLE."""
+    from paper_1909_01092_amd import _capi
+    p = workloads.channel(16, 24, kT=0.0, radius=2.5, g=(0.0, 0.0, 1.0), seed=3)
+    sim = Sim(p, "fp32")
+    sim.step(3)   # |U| passes 1/2 at the second step; stop well before the run blows up
+    with pytest.raises(_capi.LbmError) as e:
+        sim.particle_state()
+    assert e.value.code == _capi.LBM_EUNSTABLE
+    assert sim.particle_state(allow_unstable=True)["unstable"]
