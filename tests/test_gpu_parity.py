@@ -247,6 +247,7 @@ def test_single_run_full_size_one_step_fp32(Sim):
     the GPU's next step must agree to the FP32 tolerance."""
     p = workloads.SINGLE_RUN
     sim = Sim(p, "fp32")
+    sim.set_launch(256, 4)
     sim.step(30)
     f0, p0 = sim.populations(), sim.particle_state()
     ref = OracleSim(p)
@@ -318,3 +319,24 @@ def test_instability_is_reported(Sim):
         sim.particle_state()
     assert e.value.code == _capi.LBM_EUNSTABLE
     assert sim.particle_state(allow_unstable=True)["unstable"]
+
+
+def test_ensemble_full_size_one_step_fp32(Sim):
+    """The full 192-replica ensemble (32.7 M nodes, three lattice sizes) in
+    FP32: after 20 steps one replica of each size is handed to the oracle,
+    which takes one step; the GPU's next step must agree to the FP32
+    tolerance."""
+    reps = workloads.ensemble(steps_cap=64)
+    sim = Sim(reps, "fp32")
+    sim.set_launch(256, 4)
+    sim.step(20)
+    picks = (0, 128, 160)
+    states = {r: (sim.populations(r), sim.particle_state(r)) for r in picks}
+    sim.step(1)
+    for r in picks:
+        f0, p0 = states[r]
+        ref = OracleSim(reps[r])
+        ref.set_populations(f0)
+        ref.set_particle({k: p0[k] for k in ("X", "U", "W", "Pev", "Lev", "step", "n_fluid")})
+        ref.step(1)
+        compare(sim, ref, 1e-7, 2e-5, rep=r, what=f"ensemble replica {r} one step from the GPU state")
