@@ -516,22 +516,18 @@ static void series_push(orc_sim *s) {
     s->series_len++;
 }
 
-/* ------------------------------------------------------------ one step */
-static void one_step(orc_sim *s) {
+/* ------------------------------------------------------------ step 7
+ * Streaming of fpost into fnew with half-way bounce-back on walls and
+ * moving-wall bounce-back on particle nodes (momentum exchange per link:
+ * dp, torque dl about X^n, bounce-back mass flux dMbb).  Returns the
+ * number of boundary links.                                             */
+static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb[2]) {
     int64_t N = s->N;
     const orc_params *p = &s->p;
-    orc_particle *P = &s->P;
-
-    moments(s);                 /* 1 */
-    virtual_densities(s);       /* 2 */
-    double Fv[3], Tv[3];
-    forces_impl(s, s->F, Fv, Tv); /* 3 */
-    collide(s);                 /* 4-6 */
-
-    /* 7: streaming with half-way bounce-back on walls and moving-wall
-     * bounce-back on particle nodes (momentum exchange on each link)     */
+    const orc_particle *P = &s->P;
     memset(s->fnew, 0, (size_t)(2 * Q * N) * sizeof(double));
-    double dp[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dMbb[2] = {0, 0};
+    for (int a = 0; a < 3; a++) { dp[a] = 0.0; dl[a] = 0.0; }
+    dMbb[0] = dMbb[1] = 0.0;
     int64_t links = 0;
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
@@ -571,6 +567,25 @@ static void one_step(orc_sim *s) {
                     for (int l = 0; l < 2; l++) FI(s->fnew, l, i, m) = FI(s->fpost, l, i, n);
                 }
             }
+    return links;
+}
+
+/* ------------------------------------------------------------ one step */
+static void one_step(orc_sim *s) {
+    int64_t N = s->N;
+    const orc_params *p = &s->p;
+    orc_particle *P = &s->P;
+
+    moments(s);                 /* 1 */
+    virtual_densities(s);       /* 2 */
+    double Fv[3], Tv[3];
+    forces_impl(s, s->F, Fv, Tv); /* 3 */
+    collide(s);                 /* 4-6 */
+
+    /* 7: streaming with half-way bounce-back on walls and moving-wall
+     * bounce-back on particle nodes (momentum exchange on each link)     */
+    double dp[3], dl[3], dMbb[2];
+    int64_t links = stream_bounce(s, dp, dl, dMbb);
 
     /* 8: leap-frog Newton-Euler update of the sphere */
     double af[3], Fext[3];
@@ -746,4 +761,537 @@ int64_t orc_u_series(const orc_sim *s, double *u3, int64_t cap) {
     int64_t n = s->series_len < cap ? s->series_len : cap;
     memcpy(u3, s->series, (size_t)(3 * n) * sizeof(double));
     return s->series_len;
+}
+
+/* ===================================================================
+ * Adjoint (reverse-mode derivative) of nsteps steps.
+ *
+ * Objective: J = (1/nsteps) sum_{n} U_z^{n+1/2}, the time-averaged settling
+ * velocity over the steps of this call.  Parameters: the body-force vector
+ * g (three components), the Shan-Chen coupling G and the wetting offset
+ * Delta rho; grad = dJ/d(g_x, g_y, g_z, G, Delta rho).
+ *
+ * Readings.  Every relaxation time is 1.  The noise normals depend on
+ * (node, step) only and are held fixed; their amplitudes sqrt(mu rho_l b_k)
+ * are differentiated.  The particle-node, link and cover/uncover sets are
+ * piecewise constant in the particle position and are held fixed (their
+ * derivative vanishes between events); the values those sets carry
+ * (moving-wall terms, event momenta, equilibria of uncovered nodes, mass
+ * fluxes, lever arms) are differentiated.
+ *
+ * Plain form: every forward state is stored, each step is replayed, and
+ * its operations (steps 1-10 of one_step) are differentiated one by one in
+ * reverse order on full population arrays.  Parity unpinned beyond what
+ * the tests check: central differences of the forward step and the
+ * linear-response limit dJ/dg_z -> J/g_z.
+ * =================================================================== */
+
+typedef struct {
+    double *fb;        /* [2][Q][N] adjoint of the state f^{n+1} (then of f^n)   */
+    double *fnewb;     /* [2][Q][N] adjoint of fnew after streaming              */
+    double *fpostb;    /* [2][Q][N] adjoint of fpost                             */
+    double *rhob;      /* [2][N]    adjoint of the moments rho_l                 */
+    double *rtb;       /* [2][N]    adjoint of the densities seen by the force   */
+    double *Fb;        /* [2][3][N] adjoint of the node forces                   */
+} adj_arrays;
+
+static void add_cross(double out[3], const double a[3], const double b[3], double sgn) {
+    double c[3];
+    cross(a, b, c);
+    for (int a_ = 0; a_ < 3; a_++) out[a_] += sgn * c[a_];
+}
+
+/* Adjoint of the collision of one node (all relaxation times 1):
+ * fpostb[2][Q] -> adjoint of the node's populations finb[2][Q] and of its
+ * forces Fbn[2][3].                                                        */
+static void collide_node_adjoint(const orc_sim *s, const double fin[2][Q], const double F[2][3],
+                                 const double z[36], const double fpostb[2][Q],
+                                 double finb[2][Q], double Fbn[2][3]) {
+    const orc_params *p = &s->p;
+    double mu = 3.0 * p->kT;
+    double rl[2], jl[2][3];
+    for (int l = 0; l < 2; l++) {
+        rl[l] = 0.0;
+        for (int a = 0; a < 3; a++) jl[l][a] = 0.0;
+        for (int i = 0; i < Q; i++) {
+            rl[l] += s->E[0][i] * fin[l][i];
+            for (int a = 0; a < 3; a++) jl[l][a] += s->E[1 + a][i] * fin[l][i];
+        }
+    }
+    double rho = rl[0] + rl[1];
+    double u[3];
+    for (int a = 0; a < 3; a++) u[a] = (jl[0][a] + jl[1][a] + 0.5 * (F[0][a] + F[1][a])) / rho;
+    double ra = rl[0] > 0.0 ? rl[0] : 0.0, rb = rl[1] > 0.0 ? rl[1] : 0.0;
+    double amp = 0.0;
+    if (mu > 0.0 && p->noise_diffusive && rho > 0.0) amp = sqrt(mu * s->B[1] * ra * rb / rho);
+
+    double rlb[2] = {0.0, 0.0}, jlb[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    double ub[3] = {0, 0, 0}, xidb[3] = {0, 0, 0};
+    for (int l = 0; l < 2; l++) for (int a = 0; a < 3; a++) Fbn[l][a] = 0.0;
+
+    for (int l = 0; l < 2; l++) {
+        /* fout_i = w_i sum_k e_k(c_i) ms_k / b_k */
+        double msb[Q];
+        for (int k = 0; k < Q; k++) {
+            msb[k] = 0.0;
+            for (int i = 0; i < Q; i++) msb[k] += fpostb[l][i] * s->W[i] * s->E[k][i] / s->B[k];
+        }
+        double r = rl[l], sigma = l == 0 ? 1.0 : -1.0;
+        const double *Fl = F[l];
+        /* ms_0 = r */
+        rlb[l] += msb[0];
+        /* ms_{1+a} = r u_a + F_a / 2 + sigma xid_a */
+        for (int a = 0; a < 3; a++) {
+            rlb[l] += msb[1 + a] * u[a];
+            ub[a] += msb[1 + a] * r;
+            Fbn[l][a] += 0.5 * msb[1 + a];
+            xidb[a] += sigma * msb[1 + a];
+        }
+        /* m_eq: 4 r u.u, 5 r(3ux^2 - u.u), 6 r(uy^2 - uz^2), 7 r ux uy, 8 r uy uz, 9 r ux uz */
+        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        rlb[l] += msb[4] * uu;
+        for (int a = 0; a < 3; a++) ub[a] += msb[4] * r * 2.0 * u[a];
+        rlb[l] += msb[5] * (3.0 * u[0] * u[0] - uu);
+        ub[0] += msb[5] * r * (6.0 * u[0] - 2.0 * u[0]);
+        ub[1] += msb[5] * r * (-2.0 * u[1]);
+        ub[2] += msb[5] * r * (-2.0 * u[2]);
+        rlb[l] += msb[6] * (u[1] * u[1] - u[2] * u[2]);
+        ub[1] += msb[6] * r * 2.0 * u[1];
+        ub[2] += msb[6] * r * (-2.0 * u[2]);
+        rlb[l] += msb[7] * u[0] * u[1];
+        ub[0] += msb[7] * r * u[1];
+        ub[1] += msb[7] * r * u[0];
+        rlb[l] += msb[8] * u[1] * u[2];
+        ub[1] += msb[8] * r * u[2];
+        ub[2] += msb[8] * r * u[1];
+        rlb[l] += msb[9] * u[0] * u[2];
+        ub[0] += msb[9] * r * u[2];
+        ub[2] += msb[9] * r * u[0];
+        /* Guo terms Phi_k / 2: 4 u.F, 5 3uxFx - u.F, 6 uyFy - uzFz,
+         * 7 (uxFy + uyFx)/2, 8 (uyFz + uzFy)/2, 9 (uxFz + uzFx)/2 */
+        for (int a = 0; a < 3; a++) {
+            ub[a] += msb[4] * Fl[a];
+            Fbn[l][a] += msb[4] * u[a];
+            ub[a] -= msb[5] * Fl[a];
+            Fbn[l][a] -= msb[5] * u[a];
+        }
+        ub[0] += msb[5] * 3.0 * Fl[0];
+        Fbn[l][0] += msb[5] * 3.0 * u[0];
+        ub[1] += msb[6] * Fl[1];
+        Fbn[l][1] += msb[6] * u[1];
+        ub[2] -= msb[6] * Fl[2];
+        Fbn[l][2] -= msb[6] * u[2];
+        ub[0] += 0.5 * msb[7] * Fl[1]; ub[1] += 0.5 * msb[7] * Fl[0];
+        Fbn[l][1] += 0.5 * msb[7] * u[0]; Fbn[l][0] += 0.5 * msb[7] * u[1];
+        ub[1] += 0.5 * msb[8] * Fl[2]; ub[2] += 0.5 * msb[8] * Fl[1];
+        Fbn[l][2] += 0.5 * msb[8] * u[1]; Fbn[l][1] += 0.5 * msb[8] * u[2];
+        ub[0] += 0.5 * msb[9] * Fl[2]; ub[2] += 0.5 * msb[9] * Fl[0];
+        Fbn[l][2] += 0.5 * msb[9] * u[0]; Fbn[l][0] += 0.5 * msb[9] * u[2];
+        /* noise sqrt(mu r b_k) z on modes 4..18: d/dr = sqrt(mu b_k) z / (2 sqrt(r)) */
+        if (mu > 0.0 && r > 0.0)
+            for (int k = 4; k < Q; k++)
+                rlb[l] += msb[k] * sqrt(mu * s->B[k]) * z[16 * l + k - 4] / (2.0 * sqrt(r));
+    }
+    /* species-momentum noise xid = amp z_{32+a}, amp^2 = mu b_1 ra rb / rho */
+    if (amp > 0.0) {
+        double ampb = 0.0;
+        for (int a = 0; a < 3; a++) ampb += xidb[a] * z[32 + a];
+        double K0 = mu * s->B[1];
+        double dKa = K0 * (rb / rho - ra * rb / (rho * rho));
+        double dKb = K0 * (ra / rho - ra * rb / (rho * rho));
+        rlb[0] += ampb * dKa / (2.0 * amp);
+        rlb[1] += ampb * dKb / (2.0 * amp);
+    }
+    /* u = (j_A + j_B + (F_A + F_B)/2) / rho */
+    double ubu = ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2];
+    for (int l = 0; l < 2; l++) {
+        for (int a = 0; a < 3; a++) {
+            jlb[l][a] += ub[a] / rho;
+            Fbn[l][a] += 0.5 * ub[a] / rho;
+        }
+        rlb[l] -= ubu / rho;
+    }
+    /* moments rho_l = sum_i e_0 f_i, j_l = sum_i e_{1..3} f_i */
+    for (int l = 0; l < 2; l++)
+        for (int i = 0; i < Q; i++) {
+            double v = s->E[0][i] * rlb[l];
+            for (int a = 0; a < 3; a++) v += s->E[1 + a][i] * jlb[l][a];
+            finb[l][i] = v;
+        }
+}
+
+static void load_snapshot(orc_sim *s, const double *f, const orc_particle *P) {
+    memcpy(s->f, f, (size_t)(2 * Q * s->N) * sizeof(double));
+    orc_set_particle(s, P);
+}
+
+int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J) {
+    const orc_params *p = &s->p;
+    if (nsteps < 1 || p->radius <= 0.0 || p->tau_shear != 1.0 || p->tau_bulk != 1.0 ||
+        p->tau_mom != 1.0 || p->tau_ghost != 1.0)
+        return -1;
+    int64_t N = s->N;
+    size_t popn = (size_t)(2 * Q * N);
+    double *snapf = (double *)malloc((size_t)(nsteps + 1) * popn * sizeof(double));
+    orc_particle *snapP = (orc_particle *)malloc((size_t)(nsteps + 1) * sizeof(orc_particle));
+    adj_arrays A;
+    A.fb = (double *)calloc(popn, sizeof(double));
+    A.fnewb = (double *)calloc(popn, sizeof(double));
+    A.fpostb = (double *)calloc(popn, sizeof(double));
+    A.rhob = (double *)calloc((size_t)(2 * N), sizeof(double));
+    A.rtb = (double *)calloc((size_t)(2 * N), sizeof(double));
+    A.Fb = (double *)calloc((size_t)(6 * N), sizeof(double));
+    unsigned char *solid_next = (unsigned char *)calloc((size_t)N, 1);
+    if (!snapf || !snapP || !A.fb || !A.fnewb || !A.fpostb || !A.rhob || !A.rtb || !A.Fb ||
+        !solid_next) {
+        free(snapf); free(snapP); free(A.fb); free(A.fnewb); free(A.fpostb); free(A.rhob);
+        free(A.rtb); free(A.Fb); free(solid_next);
+        return -2;
+    }
+
+    /* forward sweep, storing every state */
+    double Jsum = 0.0;
+    for (int32_t k = 0; k < nsteps; k++) {
+        memcpy(snapf + (size_t)k * popn, s->f, popn * sizeof(double));
+        snapP[k] = s->P;
+        one_step(s);
+        Jsum += s->P.U[2];
+    }
+    memcpy(snapf + (size_t)nsteps * popn, s->f, popn * sizeof(double));
+    snapP[nsteps] = s->P;
+    *J = Jsum / nsteps;
+
+    double mp = p->rho_p * particle_volume(s);
+    double Ip = 0.4 * mp * p->radius * p->radius;
+    double Vp = particle_volume(s);
+    double rho_tot0 = p->rho0[0] + p->rho0[1];
+    /* d Fext / d g and d a_f / d g (both proportional to g) */
+    double cF = p->force_mode == 1 ? Vp * p->rho_p : Vp * (p->rho_p - rho_tot0);
+    double caf = p->force_mode == 1 ? 1.0 : (s->M_fluid0 > 0.0 ? -cF / s->M_fluid0 : 0.0);
+
+    double Ub[3] = {0, 0, 0}, Wb[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
+    double Pevb[3] = {0, 0, 0}, Levb[3] = {0, 0, 0};
+    double gb[3] = {0, 0, 0}, Gb = 0.0, drhob = 0.0, afb[3] = {0, 0, 0};
+    memset(A.fb, 0, popn * sizeof(double));
+
+    for (int32_t n = nsteps - 1; n >= 0; n--) {
+        /* replay steps 1-7 of step n */
+        load_snapshot(s, snapf + (size_t)n * popn, &snapP[n]);
+        const orc_particle *Pn = &snapP[n], *P1 = &snapP[n + 1];
+        moments(s);
+        virtual_densities(s);
+        double Fv[3], Tv[3];
+        forces_impl(s, s->F, Fv, Tv);
+        collide(s);
+        double dp[3], dl[3], dMbb[2];
+        stream_bounce(s, dp, dl, dMbb);
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++)
+                    solid_next[node_index(s, x, y, z)] = (unsigned char)particle_node(s, x, y, z, P1->X);
+
+        /* 10: fnew_final = fnew + w_i delta_l on Phi^{n+1},
+         * delta_l = -(dMbb + dMcov + dMunc)_l / nf                         */
+        double nf = 0.0;
+        for (int64_t m = 0; m < N; m++) nf += solid_next[m] ? 0.0 : 1.0;
+        double deltab[2] = {0.0, 0.0};
+        for (int64_t m = 0; m < N; m++) {
+            if (solid_next[m]) continue;
+            for (int l = 0; l < 2; l++)
+                for (int i = 0; i < Q; i++) deltab[l] += s->W[i] * FI(A.fb, l, i, m);
+        }
+        double dMb[2] = {-deltab[0] / nf, -deltab[1] / nf};
+        /* adjoint of fnew after the events: fb on Phi^{n+1}, zero elsewhere
+         * (covered nodes are cleared, so nothing flows back through them)  */
+        for (int64_t m = 0; m < N; m++)
+            for (int l = 0; l < 2; l++)
+                for (int i = 0; i < Q; i++)
+                    FI(A.fnewb, l, i, m) = solid_next[m] ? 0.0 : FI(A.fb, l, i, m);
+
+        /* 9: events (adjoints of U^{n+1/2}, Omega^{n+1/2}, X^{n+1} collect here) */
+        double Ub1[3], Wb1[3], Xb1[3];
+        for (int a = 0; a < 3; a++) { Ub1[a] = Ub[a]; Wb1[a] = Wb[a]; Xb1[a] = Xb[a]; }
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++) {
+                    int64_t m = node_index(s, x, y, z);
+                    double r[3];
+                    separation(s, x, y, z, P1->X, r);
+                    if (s->solid[m] && !solid_next[m]) {
+                        /* uncovered: fnew(x) = f_eq(rb, u_b), u_b = U + Omega x r */
+                        double rbv[2] = {0, 0};
+                        int cnt = 0;
+                        for (int i = 1; i < Q; i++) {
+                            int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                            if (!resolve(s, &xn, &yn, &zn)) continue;
+                            int64_t q = node_index(s, xn, yn, zn);
+                            if (s->solid[q] || solid_next[q]) continue;
+                            for (int l = 0; l < 2; l++)
+                                for (int k = 0; k < Q; k++) rbv[l] += FI(s->fnew, l, k, q);
+                            cnt++;
+                        }
+                        for (int l = 0; l < 2; l++) rbv[l] = cnt > 0 ? rbv[l] / cnt : p->rho0[l];
+                        double w[3], u[3];
+                        cross(P1->W, r, w);
+                        for (int a = 0; a < 3; a++) u[a] = P1->U[a] + w[a];
+                        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                        double rbb[2] = {0, 0}, ub[3] = {0, 0, 0};
+                        for (int l = 0; l < 2; l++)
+                            for (int i = 0; i < Q; i++) {
+                                double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+                                double fbv = FI(A.fb, l, i, m);
+                                rbb[l] += fbv * s->W[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                                for (int a = 0; a < 3; a++)
+                                    ub[a] += fbv * s->W[i] * rbv[l] *
+                                             (3.0 * CV[i][a] + 9.0 * cu * CV[i][a] - 3.0 * u[a]);
+                            }
+                        /* dMunc_l += rb_l */
+                        for (int l = 0; l < 2; l++) rbb[l] += dMb[l];
+                        /* Pev -= mom, Lev -= r x mom, mom = (rb_A + rb_B) u */
+                        double mom[3], momb[3];
+                        for (int a = 0; a < 3; a++) { mom[a] = (rbv[0] + rbv[1]) * u[a]; momb[a] = -Pevb[a]; }
+                        add_cross(momb, Levb, r, -1.0);
+                        double rbar[3] = {0, 0, 0};
+                        add_cross(rbar, mom, Levb, -1.0);
+                        for (int a = 0; a < 3; a++) {
+                            ub[a] += (rbv[0] + rbv[1]) * momb[a];
+                            rbb[0] += u[a] * momb[a];
+                            rbb[1] += u[a] * momb[a];
+                        }
+                        /* u = U + Omega x r */
+                        for (int a = 0; a < 3; a++) Ub1[a] += ub[a];
+                        add_cross(Wb1, r, ub, 1.0);
+                        add_cross(rbar, ub, P1->W, 1.0);
+                        for (int a = 0; a < 3; a++) Xb1[a] -= rbar[a];
+                        /* rb_l = mean over kept fluid neighbours of sum_k fnew */
+                        if (cnt > 0)
+                            for (int i = 1; i < Q; i++) {
+                                int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                                if (!resolve(s, &xn, &yn, &zn)) continue;
+                                int64_t q = node_index(s, xn, yn, zn);
+                                if (s->solid[q] || solid_next[q]) continue;
+                                for (int l = 0; l < 2; l++)
+                                    for (int k = 0; k < Q; k++) FI(A.fnewb, l, k, q) += rbb[l] / cnt;
+                            }
+                        /* the populations fnew(x) before the overwrite are not used */
+                        for (int l = 0; l < 2; l++)
+                            for (int i = 0; i < Q; i++) FI(A.fnewb, l, i, m) = 0.0;
+                    } else if (!s->solid[m] && solid_next[m]) {
+                        /* covered: Pev += j, Lev += r x j, dMcov_l -= rho_l */
+                        double j[3] = {0, 0, 0};
+                        for (int l = 0; l < 2; l++)
+                            for (int i = 0; i < Q; i++)
+                                for (int a = 0; a < 3; a++) j[a] += FI(s->fnew, l, i, m) * CV[i][a];
+                        double jb[3];
+                        for (int a = 0; a < 3; a++) jb[a] = Pevb[a];
+                        add_cross(jb, Levb, r, 1.0);
+                        double rbar[3] = {0, 0, 0};
+                        add_cross(rbar, j, Levb, 1.0);
+                        for (int a = 0; a < 3; a++) Xb1[a] -= rbar[a];
+                        for (int l = 0; l < 2; l++)
+                            for (int i = 0; i < Q; i++)
+                                FI(A.fnewb, l, i, m) = -dMb[l] + CV[i][0] * jb[0] + CV[i][1] * jb[1] +
+                                                       CV[i][2] * jb[2];
+                    }
+                }
+
+        /* 8: Newton-Euler.  J picks U_z^{n+1/2}; X^{n+1} = X^n + U^{n+1/2} */
+        Ub1[2] += 1.0 / nsteps;
+        for (int a = 0; a < 3; a++) Ub1[a] += Xb1[a];
+        double Fb[3] = {0, 0, 0}, Tb[3] = {0, 0, 0};
+        if (!p->fixed_velocity)
+            for (int a = 0; a < 3; a++) { Fb[a] = Ub1[a] / mp; Tb[a] = Wb1[a] / Ip; }
+        /* F = dp - Fv + Fext + Pev^n, T = dl - Tv + Lev^n; U^{n-1/2}, Omega^{n-1/2}
+         * pass through                                                       */
+        double Ub0[3], Wb0[3], Xb0[3];
+        for (int a = 0; a < 3; a++) {
+            gb[a] += cF * Fb[a];
+            Ub0[a] = Ub1[a];
+            Wb0[a] = Wb1[a];
+            Xb0[a] = Xb1[a];
+        }
+
+        /* 7: streaming adjoint */
+        memset(A.fpostb, 0, popn * sizeof(double));
+        memset(A.rhob, 0, (size_t)(2 * N) * sizeof(double));
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++) {
+                    int64_t m = node_index(s, x, y, z);
+                    if (s->solid[m]) continue;
+                    for (int l = 0; l < 2; l++) FI(A.fpostb, l, 0, m) += FI(A.fnewb, l, 0, m);
+                    for (int i = 1; i < Q; i++) {
+                        int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                        int io = opposite(i);
+                        if (!resolve(s, &xn, &yn, &zn)) {
+                            for (int l = 0; l < 2; l++) FI(A.fpostb, l, i, m) += FI(A.fnewb, l, io, m);
+                            continue;
+                        }
+                        int64_t q = node_index(s, xn, yn, zn);
+                        if (s->solid[q]) {
+                            double r[3], w[3], ubv[3];
+                            separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
+                                       Pn->X, r);
+                            cross(Pn->W, r, w);
+                            for (int a = 0; a < 3; a++) ubv[a] = Pn->U[a] + w[a];
+                            double cu = CV[i][0] * ubv[0] + CV[i][1] * ubv[1] + CV[i][2] * ubv[2];
+                            /* lp = sum_l (2 fs_l - corr_l) c_i; dp += lp; dl += r x lp */
+                            double lp[3] = {0, 0, 0}, corr[2];
+                            for (int l = 0; l < 2; l++) {
+                                corr[l] = 6.0 * s->W[i] * s->rho[l * N + m] * cu;
+                                for (int a = 0; a < 3; a++)
+                                    lp[a] += (2.0 * FI(s->fpost, l, i, m) - corr[l]) * CV[i][a];
+                            }
+                            double lpb[3];
+                            for (int a = 0; a < 3; a++) lpb[a] = Fb[a];
+                            add_cross(lpb, Tb, r, 1.0);
+                            double rbar[3] = {0, 0, 0};
+                            add_cross(rbar, lp, Tb, 1.0);
+                            double clpb = CV[i][0] * lpb[0] + CV[i][1] * lpb[1] + CV[i][2] * lpb[2];
+                            double cub = 0.0;
+                            for (int l = 0; l < 2; l++) {
+                                double a_ = FI(A.fnewb, l, io, m);
+                                FI(A.fpostb, l, i, m) += a_ + 2.0 * clpb;
+                                double corrb = -a_ - clpb - dMb[l];
+                                A.rhob[l * N + m] += 6.0 * s->W[i] * cu * corrb;
+                                cub += 6.0 * s->W[i] * s->rho[l * N + m] * corrb;
+                            }
+                            double ubb[3] = {cub * CV[i][0], cub * CV[i][1], cub * CV[i][2]};
+                            for (int a = 0; a < 3; a++) Ub0[a] += ubb[a];
+                            add_cross(Wb0, r, ubb, 1.0);
+                            add_cross(rbar, ubb, Pn->W, 1.0);
+                            for (int a = 0; a < 3; a++) Xb0[a] -= rbar[a];
+                            continue;
+                        }
+                        for (int l = 0; l < 2; l++) FI(A.fpostb, l, i, m) += FI(A.fnewb, l, i, q);
+                    }
+                }
+
+        /* 4-6: collision adjoint per fluid node */
+        memset(A.fb, 0, popn * sizeof(double));
+        for (int64_t m = 0; m < N; m++) {
+            for (int l = 0; l < 2; l++) for (int a = 0; a < 3; a++) A.Fb[(l * 3 + a) * N + m] = 0.0;
+            if (s->solid[m]) continue;
+            double fin[2][Q], F[2][3], zz[36], fpb[2][Q], finb[2][Q], Fbn[2][3];
+            for (int l = 0; l < 2; l++) {
+                for (int i = 0; i < Q; i++) { fin[l][i] = FI(s->f, l, i, m); fpb[l][i] = FI(A.fpostb, l, i, m); }
+                for (int a = 0; a < 3; a++) F[l][a] = s->F[(l * 3 + a) * N + m];
+            }
+            if (p->kT > 0.0) orc_normals(s, m, Pn->step, zz);
+            else memset(zz, 0, sizeof(zz));
+            collide_node_adjoint(s, fin, F, zz, fpb, finb, Fbn);
+            for (int l = 0; l < 2; l++) {
+                for (int i = 0; i < Q; i++) FI(A.fb, l, i, m) = finb[l][i];
+                for (int a = 0; a < 3; a++) A.Fb[(l * 3 + a) * N + m] = Fbn[l][a];
+            }
+        }
+
+        /* 3: forces F_l(x) = sum_i -G rho_l(x) w_i rt_l'(x + c_i) c_i + rho_l(x) a_f;
+         * reaction Fv, Tv (about X^n) on links into particle nodes          */
+        double af[3], Fext[3];
+        driving(s, af, Fext);
+        double Fvb[3] = {-Fb[0], -Fb[1], -Fb[2]}, Tvb[3] = {-Tb[0], -Tb[1], -Tb[2]};
+        memset(A.rtb, 0, (size_t)(2 * N) * sizeof(double));
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++) {
+                    int64_t m = node_index(s, x, y, z);
+                    if (s->solid[m]) continue;
+                    for (int l = 0; l < 2; l++)
+                        for (int a = 0; a < 3; a++) {
+                            A.rhob[l * N + m] += af[a] * A.Fb[(l * 3 + a) * N + m];
+                            afb[a] += s->rho[l * N + m] * A.Fb[(l * 3 + a) * N + m];
+                        }
+                    for (int i = 1; i < Q; i++) {
+                        int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                        int inside = resolve(s, &xn, &yn, &zn);
+                        if (!inside) {
+                            xn = x + CV[i][0]; yn = y + CV[i][1]; zn = z + CV[i][2];
+                            mirror(s, &xn, &yn, &zn);
+                        }
+                        int64_t q = node_index(s, xn, yn, zn);
+                        double linkb[2][3];
+                        for (int l = 0; l < 2; l++)
+                            for (int a = 0; a < 3; a++) linkb[l][a] = A.Fb[(l * 3 + a) * N + m];
+                        if (inside && s->solid[q]) {
+                            double r[3], fl[3] = {0, 0, 0};
+                            separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
+                                       Pn->X, r);
+                            for (int l = 0; l < 2; l++)
+                                for (int a = 0; a < 3; a++)
+                                    fl[a] += -p->G * s->rho[l * N + m] * s->W[i] * s->rt[(1 - l) * N + q] * CV[i][a];
+                            double flb[3];
+                            for (int a = 0; a < 3; a++) flb[a] = Fvb[a];
+                            add_cross(flb, Tvb, r, 1.0);
+                            double rbar[3] = {0, 0, 0};
+                            add_cross(rbar, fl, Tvb, 1.0);
+                            for (int a = 0; a < 3; a++) Xb0[a] -= rbar[a];
+                            for (int l = 0; l < 2; l++)
+                                for (int a = 0; a < 3; a++) linkb[l][a] += flb[a];
+                        }
+                        for (int l = 0; l < 2; l++) {
+                            double sl = CV[i][0] * linkb[l][0] + CV[i][1] * linkb[l][1] + CV[i][2] * linkb[l][2];
+                            double other = s->rt[(1 - l) * N + q];
+                            A.rhob[l * N + m] += -p->G * s->W[i] * other * sl;
+                            A.rtb[(1 - l) * N + q] += -p->G * s->rho[l * N + m] * s->W[i] * sl;
+                            Gb += -s->rho[l * N + m] * s->W[i] * other * sl;
+                        }
+                    }
+                }
+
+        /* 2: virtual densities (fluid: rt = rho; particle node: mean over fluid
+         * neighbours +/- Delta rho)                                           */
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++) {
+                    int64_t m = node_index(s, x, y, z);
+                    if (!s->solid[m]) {
+                        for (int l = 0; l < 2; l++) A.rhob[l * N + m] += A.rtb[l * N + m];
+                        continue;
+                    }
+                    int cnt = 0;
+                    for (int i = 1; i < Q; i++) {
+                        int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                        if (!resolve(s, &xn, &yn, &zn)) continue;
+                        if (s->solid[node_index(s, xn, yn, zn)]) continue;
+                        cnt++;
+                    }
+                    if (cnt == 0) continue;
+                    drhob += A.rtb[m] - A.rtb[N + m];
+                    for (int i = 1; i < Q; i++) {
+                        int xn = x + CV[i][0], yn = y + CV[i][1], zn = z + CV[i][2];
+                        if (!resolve(s, &xn, &yn, &zn)) continue;
+                        int64_t q = node_index(s, xn, yn, zn);
+                        if (s->solid[q]) continue;
+                        for (int l = 0; l < 2; l++) A.rhob[l * N + q] += A.rtb[l * N + m] / cnt;
+                    }
+                }
+
+        /* 1: moments rho_l = sum_i f_{l i} */
+        for (int64_t m = 0; m < N; m++) {
+            if (s->solid[m]) continue;
+            for (int l = 0; l < 2; l++)
+                for (int i = 0; i < Q; i++) FI(A.fb, l, i, m) += A.rhob[l * N + m];
+        }
+
+        for (int a = 0; a < 3; a++) {
+            Ub[a] = Ub0[a];
+            Wb[a] = Wb0[a];
+            Xb[a] = Xb0[a];
+            Pevb[a] = Fb[a];
+            Levb[a] = Tb[a];
+        }
+    }
+    for (int a = 0; a < 3; a++) gb[a] += caf * afb[a];
+    grad[0] = gb[0];
+    grad[1] = gb[1];
+    grad[2] = gb[2];
+    grad[3] = Gb;
+    grad[4] = drhob;
+
+    /* leave the simulation at the state after the last step */
+    load_snapshot(s, snapf + (size_t)nsteps * popn, &snapP[nsteps]);
+    free(snapf); free(snapP); free(A.fb); free(A.fnewb); free(A.fpostb); free(A.rhob);
+    free(A.rtb); free(A.Fb); free(solid_next);
+    return 0;
 }

@@ -67,6 +67,13 @@ void orc_observables(const orc_sim *s, double mass[2], double mom[3]);
 /* U^{n+1/2}_z series of the run so far (length = steps taken; caller sizes it) */
 int64_t orc_u_series(const orc_sim *s, double *u3, int64_t cap);
 
+/* Adjoint of nsteps steps from the current state (every relaxation time 1,
+ * radius > 0): J = (1/nsteps) sum_n U_z^{n+1/2} and
+ * grad = dJ/d(g_x, g_y, g_z, G, Delta rho).  Runs the steps forward (the
+ * simulation ends after them, as orc_step would leave it).  Returns 0, -1 for
+ * an unsupported configuration, -2 when memory runs out.                   */
+int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J);
+
 /* Building blocks exposed for the pins */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_normals(const orc_sim *s, int64_t node, int64_t step, double z[36]);

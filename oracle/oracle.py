@@ -66,6 +66,8 @@ def lib():
         _lib.orc_basis.argtypes = [d, d, d, C.POINTER(C.c_int32)]
         _lib.orc_collide_node.argtypes = [C.c_void_p, d, d, d, d]
         _lib.orc_forces.argtypes = [C.c_void_p, d]
+        _lib.orc_adjoint.restype = C.c_int
+        _lib.orc_adjoint.argtypes = [C.c_void_p, C.c_int32, d, d]
     return _lib
 
 
@@ -166,6 +168,16 @@ class OracleSim:
         out = np.empty((max(int(n), 1), 3))
         k = lib().orc_u_series(self._h, _dp(out), out.shape[0])
         return out[:k]
+
+    def adjoint(self, nsteps: int):
+        """Advance nsteps and return (J, grad): J = mean of U_z^{n+1/2} over
+        those steps, grad = dJ/d(g_x, g_y, g_z, G, Delta rho)."""
+        grad = np.empty(5)
+        J = np.empty(1)
+        rc = lib().orc_adjoint(self._h, int(nsteps), _dp(grad), _dp(J))
+        if rc != 0:
+            raise ValueError(f"oracle adjoint: unsupported configuration or no memory ({rc})")
+        return float(J[0]), grad
 
     def normals(self, node: int, step: int) -> np.ndarray:
         z = np.empty(36)

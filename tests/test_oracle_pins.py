@@ -426,3 +426,66 @@ def test_co_moving_sphere_feels_no_force(oracle_lib):
         assert np.abs(p["T"]).max() < 1e-13
         np.testing.assert_allclose(p["U"], U, rtol=1e-12)
     assert p["n_covered"] == 0 and p["n_uncovered"] == 0
+
+
+# ---------------------------------------------------------------- adjoint
+_ADJ_CASE = dict(nx=10, ny=12, nz=14, walls=3, rho0=(0.95, 0.05), init_amp=1e-3, G=1.5, kT=1e-5,
+                 seed=3, g=(0.0, 0.0, 5e-5), force_mode=0, radius=2.7, rho_p=2.0, wet_drho=0.1,
+                 X0=(4.6, 5.4, 7.3), U0=(0.02, -0.03, 0.06), W0=(0.01, 0.02, -0.01))
+
+
+def _J(oracle_lib, params, nsteps):
+    s = oracle_lib.OracleSim(params)
+    s.step(nsteps)
+    p = s.particle()
+    return s.u_series()[:, 2].mean(), (p["n_covered"], p["n_uncovered"])
+
+
+def test_adjoint_matches_central_differences(oracle_lib):
+    """dJ/d(g, G, Delta rho) of J = mean U_z^{n+1/2} against central
+    differences of the forward step, in a walled channel with noise, a
+    wetting layer and a spinning sphere that covers and uncovers nodes
+    (the event sets are the same at +h and -h, so J is smooth there)."""
+    ns = 30
+    sim = oracle_lib.OracleSim(_ADJ_CASE)
+    J, grad = sim.adjoint(ns)
+    J0, events = _J(oracle_lib, _ADJ_CASE, ns)
+    assert J == pytest.approx(J0, rel=1e-14)
+    assert min(events) > 0
+    steps = [("g", 0, 1e-6, 0), ("g", 1, 1e-6, 1), ("g", 2, 1e-6, 2),
+             ("G", None, 1e-4, 3), ("wet_drho", None, 1e-4, 4)]
+    for key, idx, h, k in steps:
+        vals = []
+        for sg in (1.0, -1.0):
+            p = dict(_ADJ_CASE)
+            if idx is None:
+                p[key] = p[key] + sg * h
+            else:
+                g = list(p["g"])
+                g[idx] += sg * h
+                p["g"] = tuple(g)
+            v, ev = _J(oracle_lib, p, ns)
+            assert ev == events
+            vals.append(v)
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(grad[k] - fd) <= 1e-6 * abs(fd), (key, idx, grad[k], fd)
+
+
+def test_adjoint_linear_response(oracle_lib):
+    """Slow settling from rest in a uniform, noise-free fluid without a
+    wetting offset: J is linear in g up to O(Re), so dJ/dg_z = J / g_z."""
+    p = dict(nx=12, ny=12, nz=16, walls=3, G=1.5, kT=0.0, g=(0.0, 0.0, 1e-6), radius=3.0,
+             rho_p=2.0, X0=(5.5, 5.5, 7.5))
+    sim = oracle_lib.OracleSim(p)
+    J, grad = sim.adjoint(20)
+    assert J > 0
+    assert abs(grad[2] - J / 1e-6) <= 1e-4 * abs(J / 1e-6)
+
+
+def test_adjoint_rejects_unsupported(oracle_lib):
+    sim = oracle_lib.OracleSim(dict(_ADJ_CASE, tau_shear=0.8))
+    with pytest.raises(ValueError):
+        sim.adjoint(2)
+    sim = oracle_lib.OracleSim(dict(_ADJ_CASE, radius=0.0))
+    with pytest.raises(ValueError):
+        sim.adjoint(2)
