@@ -200,6 +200,34 @@ int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count);
  * Synchronises the context stream. */
 int lbm_step_bytes(lbm_ctx *c, double *bytes);
 
+/* Adjoint form (reverse-mode derivative through Sec. 2 eq. lbe, eq.
+ * sc-force, the noise paragraph and the particle paragraph, and the external
+ * force of Sec. 3 eq. fp).  Runs nsteps steps from the current state and
+ * returns
+ *   *J      = (1/nsteps) sum over those steps of U_z^{n+1/2} (time-averaged
+ *             settling velocity, Sec. 4),
+ *   grad[5] = dJ/d(g_x, g_y, g_z, G, Delta rho).
+ * The noise normals of each (node, step) are held fixed (counter-based, so
+ * the replay regenerates them); particle-node, link and cover/uncover sets
+ * are held fixed (they change only at events, where J is not
+ * differentiable); every value those sets carry is differentiated.
+ * Schedule: forward sweep with a checkpoint every `segment` steps (0: 50)
+ * and after the last step; then, last segment first, each segment is
+ * replayed while its per-node densities and momenta (8 values per node and
+ * step) and sphere states are recorded, and its steps are reversed.
+ * Arithmetic: FP64 for LBM_FP64 contexts, FP32 node adjoints otherwise; the
+ * sphere and parameter adjoints are always FP64.
+ * Requirements (else LBM_EINVAL): one replica, every relaxation time 1, a
+ * sphere.  dev_adj: caller-owned device buffer, 256-byte aligned, of at
+ * least lbm_adjoint_bytes(c, nsteps, segment) bytes (LBM_ENOMEM otherwise);
+ * the library keeps no reference to it after the call.  On return the
+ * context holds the state after the nsteps steps, as lbm_step(c, nsteps)
+ * leaves it.  LBM_EUNSTABLE if the run is or goes unstable.  Synchronises
+ * the context stream. */
+int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_t *bytes);
+int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
+                double grad[5], double *J);
+
 void lbm_destroy(lbm_ctx *c);
 const char *lbm_last_error(const lbm_ctx *c);  /* NULL ctx: last lbm_init error */
 

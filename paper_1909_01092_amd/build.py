@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_k_common.hip", "lbm_k_f64.hip", "lbm_k_f32.hip", "lbm_k_f16.hip"]
+SOURCES = ["lbm_api.hip", "lbm_k_common.hip", "lbm_k_f64.hip", "lbm_k_f32.hip", "lbm_k_f16.hip",
+           "lbm_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          # packed FP32 instructions are kept out of every kernel

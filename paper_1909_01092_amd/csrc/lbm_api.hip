@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_adjoint.h"
 #include "lbm_kernels.h"
 #include "lbm_types.h"
 
@@ -386,6 +387,59 @@ int read_state(lbm_ctx *c, int r, RepState *s) {
     HIP_TRY(c, hipMemcpyAsync(s, c->d_state() + r, sizeof(RepState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+// Device memory of one adjoint call, in the caller's buffer: checkpoints at
+// the start of every segment and after the last step, the moments and states
+// recorded while a segment is replayed, two adjoint states of 8 values per
+// node, the node-force adjoint, bounding-box arrays and partial sums.
+struct AdjLayout {
+    int nseg = 0, seg = 0, nwg = 0;
+    size_t ckb = 0, recb = 0, Ab = 0;
+    size_t ck = 0, rec = 0, rst = 0, A[2] = {0, 0}, Fb = 0, vt = 0, vinv = 0, vtb = 0, ubn = 0,
+           partA = 0, partB = 0, adj = 0, total = 0;
+};
+
+int adj_check(lbm_ctx *c, int32_t nsteps, int32_t segment) {
+    if (!c) return LBM_EINVAL;
+    if (c->nrep != 1) return fail(c, LBM_EINVAL, "the adjoint takes a single-replica context");
+    if (!c->tau1) return fail(c, LBM_EINVAL, "the adjoint needs every relaxation time equal to 1");
+    if (!c->desc[0].has_particle) return fail(c, LBM_EINVAL, "the adjoint needs a sphere (radius > 0)");
+    if (nsteps < 1) return fail(c, LBM_EINVAL, "nsteps must be >= 1");
+    if (segment < 0) return fail(c, LBM_EINVAL, "segment must be >= 0 (0: 50 steps)");
+    return LBM_OK;
+}
+
+AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
+    AdjLayout A;
+    A.seg = std::min(segment > 0 ? segment : 50, nsteps);
+    A.nseg = (nsteps + A.seg - 1) / A.seg;
+    const int64_t N = c->desc[0].N;
+    const size_t te = c->prec == LBM_FP64 ? 8 : 4;
+    const int64_t S3 = c->L.S3tot;
+    A.nwg = (int)((N + 255) / 256);
+    lbm_checkpoint_bytes(c, &A.ckb);
+    A.ckb = align_up(A.ckb);
+    A.recb = align_up(8 * N * te);
+    A.Ab = align_up(8 * N * te);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    A.ck = take(A.ckb * (A.nseg + 1));
+    A.rec = take(A.recb * (A.seg + 1));
+    A.rst = take(sizeof(RepState) * (A.seg + 1));
+    A.A[0] = take(A.Ab);
+    A.A[1] = take(A.Ab);
+    A.Fb = take(6 * N * te);
+    A.vt = take(sizeof(double) * 2 * S3);
+    A.vinv = take(sizeof(double) * S3);
+    A.vtb = take(sizeof(double) * 2 * S3);
+    A.ubn = take(sizeof(double) * 2 * S3);
+    A.partA = take(sizeof(double) * ADJ_PA * A.nwg);
+    A.partB = take(sizeof(double) * ADJ_PB * A.nwg);
+    A.adj = take(sizeof(AdjState));
+    A.total = o;
+    return A;
 }
 
 }  // namespace
@@ -876,6 +930,100 @@ LBM_API int lbm_set_overlap(lbm_ctx *c, int32_t enable) {
     if (!c) return LBM_EINVAL;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return set_split(c, enable != 0);
+}
+
+LBM_API int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_t *bytes) {
+    const int rc = adj_check(c, nsteps, segment);
+    if (rc != LBM_OK) return rc;
+    if (!bytes) return fail(c, LBM_EINVAL, "bytes is NULL");
+    *bytes = adj_plan(c, nsteps, segment).total;
+    return LBM_OK;
+}
+
+LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
+                        double grad[5], double *J) {
+    int rc = adj_check(c, nsteps, segment);
+    if (rc != LBM_OK) return rc;
+    if (!grad || !J) return fail(c, LBM_EINVAL, "grad and J must not be NULL");
+    const AdjLayout A = adj_plan(c, nsteps, segment);
+    if (!dev_adj || ((uintptr_t)dev_adj % ALIGN) != 0)
+        return fail(c, LBM_ENOMEM, "adjoint buffer must be a 256-byte aligned device pointer");
+    if (adj_bytes < A.total)
+        return fail(c, LBM_ENOMEM, fmt("adjoint buffer of %zu bytes is smaller than the %zu needed",
+                                       adj_bytes, A.total));
+    RepState st0;
+    rc = read_state(c, 0, &st0);
+    if (rc != LBM_OK) return rc;
+    if (st0.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run is unstable");
+    char *w = reinterpret_cast<char *>(dev_adj);
+    auto ck = [&](int s) { return w + A.ck + (size_t)s * A.ckb; };
+    auto seg_len = [&](int s) { return std::min(A.seg, nsteps - s * A.seg); };
+    // forward sweep, checkpoint at the start of every segment and at the end
+    for (int s = 0; s < A.nseg; s++) {
+        if ((rc = lbm_checkpoint(c, ck(s))) != LBM_OK) return rc;
+        if ((rc = lbm_step(c, seg_len(s))) != LBM_OK) return rc;
+    }
+    if ((rc = lbm_checkpoint(c, ck(A.nseg))) != LBM_OK) return rc;
+    HIP_TRY(c, hipMemsetAsync(w + A.adj, 0, sizeof(AdjState), c->stream));
+    HIP_TRY(c, hipMemsetAsync(w + A.A[0], 0, A.Ab, c->stream));
+
+    const lbm_params &q = c->p[0];
+    const RepDesc &D = c->desc[0];
+    const double V = 4.0 / 3.0 * M_PI * q.radius * q.radius * q.radius;
+    const double cF = q.force_mode == 1 ? V * q.rho_p : V * (q.rho_p - (q.rho0[0] + q.rho0[1]));
+    const double caf = q.force_mode == 1 ? 1.0 : (D.M0 > 0.0 ? -cF / D.M0 : 0.0);
+    AdjArgs aa;
+    aa.desc = c->d_desc();
+    aa.adj = reinterpret_cast<AdjState *>(w + A.adj);
+    aa.cF = cF;
+    aa.invN = 1.0 / nsteps;
+    aa.Fb = w + A.Fb;
+    aa.vt = reinterpret_cast<double *>(w + A.vt);
+    aa.vinv = reinterpret_cast<double *>(w + A.vinv);
+    aa.vtb = reinterpret_cast<double *>(w + A.vtb);
+    aa.ubn = reinterpret_cast<double *>(w + A.ubn);
+    aa.partA = reinterpret_cast<double *>(w + A.partA);
+    aa.partB = reinterpret_cast<double *>(w + A.partB);
+    aa.nwg = A.nwg;
+    RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
+    int an = 0;  // buffer holding the adjoint of the state after the step being reversed
+    for (int s = A.nseg - 1; s >= 0; s--) {
+        if ((rc = lbm_restore(c, ck(s))) != LBM_OK) return rc;
+        const int K = seg_len(s);
+        for (int k = 0; k <= K; k++) {
+            RecArgs ra;
+            ra.desc = c->d_desc();
+            ra.state = c->d_state();
+            ra.src = c->d_pop(c->cur);
+            ra.rec = w + A.rec + (size_t)k * A.recb;
+            ra.st_out = rst + k;
+            hipError_t e = launch_adj_record(c->prec, ra, D.N, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
+            if (k < K && (rc = enqueue_step(c, false)) != LBM_OK) return rc;
+        }
+        for (int k = K - 1; k >= 0; k--) {
+            aa.stn = rst + k;
+            aa.stn1 = rst + k + 1;
+            aa.recn = w + A.rec + (size_t)k * A.recb;
+            aa.recn1 = w + A.rec + (size_t)(k + 1) * A.recb;
+            aa.Anext = w + A.A[an];
+            aa.Acur = w + A.A[1 - an];
+            hipError_t e = launch_adj_step(c->prec, aa, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step launch");
+            an = 1 - an;
+        }
+    }
+    if ((rc = lbm_restore(c, ck(A.nseg))) != LBM_OK) return rc;
+    AdjState h;
+    HIP_TRY(c, hipMemcpyAsync(&h, w + A.adj, sizeof(AdjState), hipMemcpyDeviceToHost, c->stream));
+    RepState st1;
+    if ((rc = read_state(c, 0, &st1)) != LBM_OK) return rc;
+    for (int a = 0; a < 3; a++) grad[a] = h.grad[a] + caf * h.afb[a];
+    grad[3] = h.grad[3];
+    grad[4] = h.grad[4];
+    *J = h.Jsum / nsteps;
+    if (st1.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run went unstable");
+    return LBM_OK;
 }
 
 LBM_API void lbm_destroy(lbm_ctx *c) {

@@ -191,6 +191,22 @@ class Simulation:
                                            C.byref(n)))
         return buf[: n.value].copy()
 
+    # -- adjoint form
+    def adjoint(self, nsteps: int, segment: int = 0):
+        """Advance nsteps (as step() would) and return (J, grad): J = mean of
+        U_z^{n+1/2} over those steps, grad = dJ/d(g_x, g_y, g_z, G, Delta rho)
+        (lbm_adjoint; segment = checkpoint interval, 0 = 50 steps)."""
+        import torch
+        n = C.c_size_t()
+        self._check(self._lib.lbm_adjoint_bytes(self._ctx, int(nsteps), int(segment), C.byref(n)))
+        buf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        grad = np.empty(5)
+        J = C.c_double()
+        self._check(self._lib.lbm_adjoint(self._ctx, int(nsteps), int(segment), C.c_void_p(ptr), n.value,
+                                          grad.ctypes.data_as(C.POINTER(C.c_double)), C.byref(J)))
+        return J.value, grad
+
     # -- checkpoints (device tensors)
     def checkpoint(self):
         import torch
