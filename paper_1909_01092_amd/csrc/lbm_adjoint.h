@@ -29,9 +29,22 @@ struct AdjState {
     double Jsum;                 // sum of U_z^{n+1/2} over the reversed steps
 };
 
+// Forward values of a fluid node at step n rebuilt from the recorded
+// moments: density deviations and densities, momenta, forces, the sums
+// sum_i w_i rho~_l(x + c_i) c_i, velocity, species-momentum noise and its
+// normals and amplitude; links through a wall / into the sphere (bit i).
+template <typename T>
+struct NodeFwd {
+    T rd[2], rl[2], jl[2][3], F[2][3], sv[2][3], u[3], xid[3], zd[4], ampf;
+    uint32_t wall, link;
+};
+constexpr size_t NODE_FWD_BYTES = sizeof(NodeFwd<double>);
+
 constexpr int ADJ_PA = 13;   // doubles per workgroup partial of the local kernel
 constexpr int ADJ_PB = 2;    // doubles per workgroup partial of the gather kernel
-constexpr int ADJ_BOX = 1024;  // threads of the bounding-box kernels
+constexpr int ADJ_PE = 9;    // doubles of an event partial (stride PART per workgroup)
+constexpr int ADJ_PC = 3;    // doubles of a wetting-chain partial (stride PART per workgroup)
+constexpr int ADJ_BOX = 1024;  // threads of the summing kernel
 
 struct AdjArgs {
     const RepDesc *desc;
@@ -49,9 +62,16 @@ struct AdjArgs {
     double *vinv;            // box: 1 / fluid-neighbour count of particle nodes (0: none) [S^3]
     double *vtb;             // box: adjoint of the wetting-layer densities [2][S^3]
     double *ubn;             // box: uncovered-node density adjoint per kept neighbour [2][S^3]
+    void *nfw;               // box: NodeFwd<T> of the nodes with sphere links [S^3]
     double *partA;           // [nwg][ADJ_PA]
     double *partB;           // [nwg][ADJ_PB]
+    double *partE;           // [nbw][PART] event partials
+    double *partC;           // [nbw][PART] wetting-chain partials
+    double *partL;           // [nbw][PART] link partials (same slots as partA)
+    double *partM;           // [nmw][PART] wall-mirror partials
     int32_t nwg;             // workgroups of the node kernels (256 threads, one node each)
+    int32_t nbw;             // workgroups of the box kernels (256 threads, one box node each)
+    int32_t nmw;             // workgroups of the wall-face kernel (256 threads, one face node each)
 };
 
 struct RecArgs {

@@ -395,10 +395,10 @@ int read_state(lbm_ctx *c, int r, RepState *s) {
 // recorded while a segment is replayed, two adjoint states of 8 values per
 // node, the node-force adjoint, bounding-box arrays and partial sums.
 struct AdjLayout {
-    int nseg = 0, seg = 0, nwg = 0;
+    int nseg = 0, seg = 0, nwg = 0, nbw = 0, nmw = 0;
     size_t ckb = 0, recb = 0, Ab = 0;
-    size_t ck = 0, rec = 0, rst = 0, A[2] = {0, 0}, Fb = 0, vt = 0, vinv = 0, vtb = 0, ubn = 0,
-           partA = 0, partB = 0, adj = 0, total = 0;
+    size_t ck = 0, rec = 0, rst = 0, A[2] = {0, 0}, Fb = 0, vt = 0, vinv = 0, vtb = 0, ubn = 0, nfw = 0,
+           partA = 0, partB = 0, partE = 0, partC = 0, partL = 0, partM = 0, adj = 0, total = 0;
 };
 
 int adj_check(lbm_ctx *c, int32_t nsteps, int32_t segment) {
@@ -419,6 +419,15 @@ AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     const size_t te = c->prec == LBM_FP64 ? 8 : 4;
     const int64_t S3 = c->L.S3tot;
     A.nwg = (int)((N + 255) / 256);
+    A.nbw = (int)((S3 + 255) / 256);
+    {
+        const lbm_params &q = c->p[0];
+        const int64_t nn[3] = {q.nx, q.ny, q.nz};
+        int64_t faces = 0;
+        for (int ax = 0; ax < 3; ax++)
+            if (q.walls & (1u << ax)) faces += 2 * nn[(ax + 1) % 3] * nn[(ax + 2) % 3];
+        A.nmw = (int)std::max<int64_t>(1, (faces + 255) / 256);
+    }
     lbm_checkpoint_bytes(c, &A.ckb);
     A.ckb = align_up(A.ckb);
     A.recb = align_up(8 * N * te);
@@ -435,8 +444,13 @@ AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     A.vinv = take(sizeof(double) * S3);
     A.vtb = take(sizeof(double) * 2 * S3);
     A.ubn = take(sizeof(double) * 2 * S3);
+    A.nfw = take(NODE_FWD_BYTES * S3);
     A.partA = take(sizeof(double) * ADJ_PA * A.nwg);
     A.partB = take(sizeof(double) * ADJ_PB * A.nwg);
+    A.partE = take(sizeof(double) * PART * A.nbw);
+    A.partC = take(sizeof(double) * PART * A.nbw);
+    A.partL = take(sizeof(double) * PART * A.nbw);
+    A.partM = take(sizeof(double) * PART * A.nmw);
     A.adj = take(sizeof(AdjState));
     A.total = o;
     return A;
@@ -982,9 +996,16 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     aa.vinv = reinterpret_cast<double *>(w + A.vinv);
     aa.vtb = reinterpret_cast<double *>(w + A.vtb);
     aa.ubn = reinterpret_cast<double *>(w + A.ubn);
+    aa.nfw = w + A.nfw;
     aa.partA = reinterpret_cast<double *>(w + A.partA);
     aa.partB = reinterpret_cast<double *>(w + A.partB);
+    aa.partE = reinterpret_cast<double *>(w + A.partE);
+    aa.partC = reinterpret_cast<double *>(w + A.partC);
+    aa.partL = reinterpret_cast<double *>(w + A.partL);
+    aa.partM = reinterpret_cast<double *>(w + A.partM);
     aa.nwg = A.nwg;
+    aa.nbw = A.nbw;
+    aa.nmw = A.nmw;
     RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
     int an = 0;  // buffer holding the adjoint of the state after the step being reversed
     for (int s = A.nseg - 1; s >= 0; s--) {

@@ -105,3 +105,53 @@ def test_adjoint_rejects_unsupported(Sim):
     sim = Sim([EVENTS, EVENTS], "fp64")
     with pytest.raises(LbmError):
         sim.adjoint(3)
+
+
+def _J_forward(Sim, p, steps, prec="fp64"):
+    s = Sim(p, prec)
+    s.step(steps)
+    st = s.particle_state()
+    return s.u_series()[-steps:, 2].mean(), (st["n_covered"], st["n_uncovered"])
+
+
+def test_adjoint_full_size_central_differences(Sim):
+    """48 x 48 x 192 channel (R = 6, kT = 1e-5, g = 5e-5), 200 steps: the FP64
+    adjoint against central differences of the GPU's own FP64 forward (same
+    event sets at +h and -h), and the FP32 adjoint against the FP64 one."""
+    p, steps = workloads.ADJOINT, 200
+    print(f"full size {p['nx']}x{p['ny']}x{p['nz']} steps {steps}", flush=True)
+    J, g = Sim(p, "fp64").adjoint(steps)
+    J0, ev0 = _J_forward(Sim, p, steps)
+    assert abs(J - J0) <= 1e-13 * abs(J0)
+    for k, h, tol in [(2, 5e-9, 1e-8), (3, 1e-4, 1e-5), (4, 1e-4, 1e-6)]:
+        vals = []
+        for sg in (1.0, -1.0):
+            q = dict(p)
+            if k == 2:
+                q["g"] = (0.0, 0.0, p["g"][2] + sg * h)
+            elif k == 3:
+                q["G"] = p["G"] + sg * h
+            else:
+                q["wet_drho"] = p["wet_drho"] + sg * h
+            v, ev = _J_forward(Sim, q, steps)
+            assert ev == ev0
+            vals.append(v)
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print(f"  grad[{k}] adjoint {g[k]: .12e} central difference {fd: .12e}", flush=True)
+        assert abs(g[k] - fd) <= tol * abs(fd), (k, g[k], fd)
+    J32, g32 = Sim(p, "fp32").adjoint(steps)
+    print(f"  fp32 {g32} fp64 {g}", flush=True)
+    assert abs(J32 - J) <= 1e-5 * abs(J)
+    for k in range(5):
+        assert abs(g32[k] - g[k]) <= 2e-4 * abs(g[k]), (k, g32[k], g[k])
+
+
+def test_settling_velocity_autograd(Sim):
+    import torch
+    from paper_1909_01092_amd.autograd import settling_velocity
+    theta = torch.tensor([0.0, 0.0, 5e-5, 1.5, 0.1], dtype=torch.float64, requires_grad=True)
+    J = settling_velocity(theta, EVENTS, 30, "fp64")
+    J.backward()
+    Jo, go = _oracle(EVENTS, 30)
+    assert abs(J.item() - Jo) <= 1e-12 * abs(Jo)
+    assert np.allclose(theta.grad.numpy(), go, rtol=1e-9, atol=0.0)
