@@ -1,6 +1,6 @@
 """Throughput of the fluctuating two-component D3Q19 + sphere step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|ensemble|large|parity]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|ensemble|large|parity|adjoint]
 
 Prints ONE JSON line: MLUPS (replica node updates per second / 1e6, both
 components of a node counted once) for the chosen workload with all inputs
@@ -11,6 +11,11 @@ resident in HBM, plus
                 timed region, against the 8 TB/s HBM peak;
   cpu_baseline: the FP64 CPU oracle timed on a bounded sample of the same
                 workload on this host (single thread).
+--workload adjoint times lbm_adjoint (1000 steps, checkpoint every 50) on
+the 48x48x192 channel instead: MLUPS of the whole adjoint call (forward
+sweep, replays and reverse sweep; each step counted once), its cost against
+plain steps of the same channel, and the roofline of the adjoint's node
+kernel.
 """
 import argparse
 import hashlib
@@ -86,6 +91,72 @@ def cpu_baseline(reps, budget_s=15.0):
     return {"value": round(N * steps / el / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} step(s) of one {p['nx']}x{p['ny']}x{p['nz']} replica of the same "
                       f"workload in FP64 ({el:.1f} s; init {t_init:.1f} s excluded)"}
+
+
+# algorithmic bytes per node of the adjoint node kernel (FP32): recorded
+# moments (8 values) and adjoint state after the step (8) read, adjoint state
+# before the step (8) and node-force adjoint (6) written; the neighbours'
+# values are the same arrays read again through the caches
+ADJ_LOCAL_BYTES_PER_NODE = (8 + 8 + 8 + 6) * 4
+
+
+def adjoint_bench(torch, args, steps, segment=50):
+    from oracle.oracle import OracleSim
+    from paper_1909_01092_amd import workloads as w
+    from paper_1909_01092_amd.sim import Simulation
+    p = w.ADJOINT
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    sim = Simulation(p, precision="fp32", device="cuda:0", stream=torch.cuda.Stream())
+    if args.zchunk:
+        sim.set_launch(args.block, args.zchunk)
+    elif args.autotune > 0:
+        sim.autotune(steps_per_trial=args.autotune, preserve=False)
+    block, cz = sim.get_launch()
+    sim.adjoint(min(args.warmup, 50), segment)  # warm-up
+    sim.sync()
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, grad = sim.adjoint(steps, segment)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern_ms, nlaunch = sim.timing_read()
+    sim.timing(False)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    el_fwd = time.perf_counter() - t0
+    unstable = sim.particle_state(0, allow_unstable=True)["unstable"]
+    sim.close()
+    bpl = ADJ_LOCAL_BYTES_PER_NODE * nodes
+    achieved = bpl / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS (2-comp D3Q19), adjoint form vs plain", "value": round(nodes * steps / el / 1e6, 2),
+        "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 50),
+        "ms_per_step": round(el * 1e3 / steps, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "adjoint 48x48x192 channel, R=6, kT=1e-5, g=5e-5, G=1.5, FP32 "
+                               f"deviations, checkpoint every {segment} steps",
+                   "replicas": 1, "nodes": nodes, "precision": "fp32", "block": block, "zchunk": cz,
+                   "unstable": unstable},
+        "adjoint": {"J": J, "grad_g_xyz_G_drho": [float(v) for v in grad], "segment": segment,
+                    "plain_ms_per_step": round(el_fwd * 1e3 / steps, 5),
+                    "cost_vs_plain": round(el / el_fwd, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_adj_local",
+                     "kernel_ms": round(kern_ms, 5), "launches": nlaunch, "bytes_per_launch": bpl},
+    }
+    if not args.no_cpu:
+        k = 2
+        osim = OracleSim(p)
+        t0 = time.perf_counter()
+        osim.adjoint(k)
+        oel = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nodes * k / oel / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle adjoint of {k} steps of the same 48x48x192 channel "
+                                         f"in FP64 ({oel:.1f} s, every state stored)"}
+    print(json.dumps(out), flush=True)
 
 
 def langevin_stats(sim, reps, steps, skip):
@@ -177,7 +248,7 @@ def copy_calibration(torch, mib, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2000; adjoint: 1000)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="single")
     ap.add_argument("--zchunk", type=int, default=0, help="fixed main-kernel z-chunk (skips the autotuner)")
@@ -204,11 +275,15 @@ def main():
 
     import torch
     if args.copy_mib:
-        copy_calibration(torch, args.copy_mib, args.steps, args.warmup)
+        copy_calibration(torch, args.copy_mib, args.steps or 2000, args.warmup)
         return
     if args.fp16_error:
         fp16_error(torch, args.fp16_error)
         return
+    if args.workload == "adjoint":
+        adjoint_bench(torch, args, args.steps or 1000)
+        return
+    args.steps = args.steps or 2000
     from paper_1909_01092_amd.sim import Simulation
     reps, prec, desc = workload(args.workload)
     stream = torch.cuda.Stream()

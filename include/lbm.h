@@ -223,7 +223,9 @@ int lbm_step_bytes(lbm_ctx *c, double *bytes);
  * the library keeps no reference to it after the call.  On return the
  * context holds the state after the nsteps steps, as lbm_step(c, nsteps)
  * leaves it.  LBM_EUNSTABLE if the run is or goes unstable.  Synchronises
- * the context stream. */
+ * the context stream.  While lbm_timing is enabled, the launches this call
+ * times (lbm_timing_read) are those of the adjoint's node kernel, one per
+ * reversed step; its forward sweep and replays run untimed. */
 int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_t *bytes);
 int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
                 double grad[5], double *J);

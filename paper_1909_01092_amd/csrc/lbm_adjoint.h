@@ -83,6 +83,7 @@ struct RecArgs {
 };
 
 hipError_t launch_adj_record(int prec, const RecArgs &a, int64_t N, hipStream_t s);
-hipError_t launch_adj_step(int prec, const AdjArgs &a, hipStream_t s);
+// one reversed step; e0 / e1 (optional) are recorded around the node kernel k_adj_local
+hipError_t launch_adj_step(int prec, const AdjArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace lbm

@@ -949,10 +949,18 @@ hipError_t launch_record_t(const RecArgs &a, int64_t N, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_step_t(const AdjArgs &a, hipStream_t s) {
+hipError_t launch_step_t(const AdjArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     hipLaunchKernelGGL((k_adj_events<T>), dim3(a.nbw), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_kept<T>), dim3(a.nbw), dim3(NB), 0, s, a);
+    if (e0) {
+        const hipError_t e = hipEventRecord(e0, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_adj_local<T>), dim3(a.nwg), dim3(NB), 0, s, a);
+    if (e1) {
+        const hipError_t e = hipEventRecord(e1, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_adj_links<T>), dim3(a.nbw), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_gather<T>), dim3(a.nwg), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_mirror<T>), dim3(a.nmw), dim3(NB), 0, s, a);
@@ -969,8 +977,8 @@ hipError_t launch_adj_record(int prec, const RecArgs &a, int64_t N, hipStream_t 
     return launch_record_t<_Float16, float>(a, N, s);
 }
 
-hipError_t launch_adj_step(int prec, const AdjArgs &a, hipStream_t s) {
-    return prec == 0 ? launch_step_t<double>(a, s) : launch_step_t<float>(a, s);
+hipError_t launch_adj_step(int prec, const AdjArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return prec == 0 ? launch_step_t<double>(a, s, e0, e1) : launch_step_t<float>(a, s, e0, e1);
 }
 
 }  // namespace lbm

@@ -970,6 +970,15 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     if (rc != LBM_OK) return rc;
     if (st0.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run is unstable");
     char *w = reinterpret_cast<char *>(dev_adj);
+    // with timing on, the timed launches of this call are the adjoint node
+    // kernel's (the forward sweep and the replays run untimed)
+    const bool timed = c->timing;
+    struct TimingOff {
+        lbm_ctx *c;
+        bool was;
+        ~TimingOff() { c->timing = was; }
+    } keep{c, c->timing};
+    c->timing = false;
     auto ck = [&](int s) { return w + A.ck + (size_t)s * A.ckb; };
     auto seg_len = [&](int s) { return std::min(A.seg, nsteps - s * A.seg); };
     // forward sweep, checkpoint at the start of every segment and at the end
@@ -1029,7 +1038,20 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
             aa.recn1 = w + A.rec + (size_t)(k + 1) * A.recb;
             aa.Anext = w + A.A[an];
             aa.Acur = w + A.A[1 - an];
-            hipError_t e = launch_adj_step(c->prec, aa, c->stream);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                if (c->ev_used + 2 > c->ev.size()) {
+                    for (int q = 0; q < 256; q++) {
+                        hipEvent_t ev;
+                        HIP_TRY(c, hipEventCreate(&ev));
+                        c->ev.push_back(ev);
+                    }
+                }
+                e0 = c->ev[c->ev_used];
+                e1 = c->ev[c->ev_used + 1];
+                c->ev_used += 2;
+            }
+            hipError_t e = launch_adj_step(c->prec, aa, c->stream, e0, e1);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint step launch");
             an = 1 - an;
         }
