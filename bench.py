@@ -122,6 +122,13 @@ def adjoint_bench(torch, args, steps, segment=50):
     el = time.perf_counter() - t0
     kern_ms, nlaunch = sim.timing_read()
     sim.timing(False)
+    # one segment: every step's moments recorded (8 FP32 per node and step),
+    # so the forward steps run once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint(steps, steps)
+    torch.cuda.synchronize()
+    el_one = time.perf_counter() - t0
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
@@ -141,7 +148,9 @@ def adjoint_bench(torch, args, steps, segment=50):
                    "unstable": unstable},
         "adjoint": {"J": J, "grad_g_xyz_G_drho": [float(v) for v in grad], "segment": segment,
                     "plain_ms_per_step": round(el_fwd * 1e3 / steps, 5),
-                    "cost_vs_plain": round(el / el_fwd, 3)},
+                    "cost_vs_plain": round(el / el_fwd, 3),
+                    "one_segment_ms_per_step": round(el_one * 1e3 / steps, 5),
+                    "one_segment_cost_vs_plain": round(el_one / el_fwd, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_adj_local",
                      "kernel_ms": round(kern_ms, 5), "launches": nlaunch, "bytes_per_launch": bpl},

@@ -212,9 +212,11 @@ int lbm_step_bytes(lbm_ctx *c, double *bytes);
  * are held fixed (they change only at events, where J is not
  * differentiable); every value those sets carry is differentiated.
  * Schedule: forward sweep with a checkpoint every `segment` steps (0: 50)
- * and after the last step; then, last segment first, each segment is
- * replayed while its per-node densities and momenta (8 values per node and
- * step) and sphere states are recorded, and its steps are reversed.
+ * and after the last step; the sweep records the last segment's per-node
+ * densities and momenta (8 values per node and step) and sphere states.
+ * Then, last segment first, each segment's steps are reversed, every other
+ * segment being replayed from its checkpoint and recorded first.  With
+ * segment >= nsteps the forward steps run once.
  * Arithmetic: FP64 for LBM_FP64 contexts, FP32 node adjoints otherwise; the
  * sphere and parameter adjoints are always FP64.
  * Requirements (else LBM_EINVAL): one replica, every relaxation time 1, a

@@ -981,10 +981,30 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     c->timing = false;
     auto ck = [&](int s) { return w + A.ck + (size_t)s * A.ckb; };
     auto seg_len = [&](int s) { return std::min(A.seg, nsteps - s * A.seg); };
-    // forward sweep, checkpoint at the start of every segment and at the end
+    RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
+    // K steps from the current state, recording the moments and the sphere
+    // state before every step and after the last
+    auto record_segment = [&](int K) -> int {
+        for (int k = 0; k <= K; k++) {
+            RecArgs ra;
+            ra.desc = c->d_desc();
+            ra.state = c->d_state();
+            ra.src = c->d_pop(c->cur);
+            ra.rec = w + A.rec + (size_t)k * A.recb;
+            ra.st_out = rst + k;
+            hipError_t e = launch_adj_record(c->prec, ra, c->desc[0].N, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
+            int r;
+            if (k < K && (r = enqueue_step(c, false)) != LBM_OK) return r;
+        }
+        return LBM_OK;
+    };
+    // forward sweep: a checkpoint at the start of every segment and at the
+    // end; the last segment is recorded on the way, so it is not replayed
     for (int s = 0; s < A.nseg; s++) {
         if ((rc = lbm_checkpoint(c, ck(s))) != LBM_OK) return rc;
-        if ((rc = lbm_step(c, seg_len(s))) != LBM_OK) return rc;
+        rc = s + 1 < A.nseg ? lbm_step(c, seg_len(s)) : record_segment(seg_len(s));
+        if (rc != LBM_OK) return rc;
     }
     if ((rc = lbm_checkpoint(c, ck(A.nseg))) != LBM_OK) return rc;
     HIP_TRY(c, hipMemsetAsync(w + A.adj, 0, sizeof(AdjState), c->stream));
@@ -1015,21 +1035,12 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     aa.nwg = A.nwg;
     aa.nbw = A.nbw;
     aa.nmw = A.nmw;
-    RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
     int an = 0;  // buffer holding the adjoint of the state after the step being reversed
     for (int s = A.nseg - 1; s >= 0; s--) {
-        if ((rc = lbm_restore(c, ck(s))) != LBM_OK) return rc;
         const int K = seg_len(s);
-        for (int k = 0; k <= K; k++) {
-            RecArgs ra;
-            ra.desc = c->d_desc();
-            ra.state = c->d_state();
-            ra.src = c->d_pop(c->cur);
-            ra.rec = w + A.rec + (size_t)k * A.recb;
-            ra.st_out = rst + k;
-            hipError_t e = launch_adj_record(c->prec, ra, D.N, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
-            if (k < K && (rc = enqueue_step(c, false)) != LBM_OK) return rc;
+        if (s + 1 < A.nseg) {  // replay (the last segment was recorded by the sweep)
+            if ((rc = lbm_restore(c, ck(s))) != LBM_OK) return rc;
+            if ((rc = record_segment(K)) != LBM_OK) return rc;
         }
         for (int k = K - 1; k >= 0; k--) {
             aa.stn = rst + k;
