@@ -27,6 +27,8 @@ struct AdjState {
     double grad[5];              // dJ/d(g_x, g_y, g_z, G, Delta rho) so far (g: external-force part)
     double afb[3];               // adjoint of the body-force acceleration of the fluid
     double Jsum;                 // sum of U_z^{n+1/2} over the reversed steps
+    uint32_t done;               // completion counter of the wetting-chain kernel (0 between steps)
+    uint32_t pad;
 };
 
 // Forward values of a fluid node at step n rebuilt from the recorded
@@ -44,7 +46,6 @@ constexpr int ADJ_PA = 13;   // doubles per workgroup partial of the local kerne
 constexpr int ADJ_PB = 2;    // doubles per workgroup partial of the gather kernel
 constexpr int ADJ_PE = 9;    // doubles of an event partial (stride PART per workgroup)
 constexpr int ADJ_PC = 3;    // doubles of a wetting-chain partial (stride PART per workgroup)
-constexpr int ADJ_BOX = 1024;  // threads of the summing kernel
 
 struct AdjArgs {
     const RepDesc *desc;
@@ -67,7 +68,7 @@ struct AdjArgs {
     double *partB;           // [nwg][ADJ_PB]
     double *partE;           // [nbw][PART] event partials
     double *partC;           // [nbw][PART] wetting-chain partials
-    double *partL;           // [nbw][PART] link partials (same slots as partA)
+    double *partL;           // [2 nbw][PART] link partials (same slots as partA)
     double *partM;           // [nmw][PART] wall-mirror partials
     int32_t nwg;             // workgroups of the node kernels (256 threads, one node each)
     int32_t nbw;             // workgroups of the box kernels (256 threads, one box node each)

@@ -26,8 +26,9 @@
 // (collision, force and link adjoints; Shan-Chen gather from the
 // neighbours' force adjoints; k_adj_mirror over the walled faces for the
 // wall-mirror sources), k_adj_links over the box (moving-wall and
-// wetting-reaction terms of the sphere links), k_adj_chain over the box (wetting-layer
-// chain) and k_adj_sum (fixed-order sums into the adjoint state).
+// wetting-reaction terms of the sphere links), and k_adj_chain over the box
+// (wetting-layer chain; its last workgroup makes the fixed-order sums into
+// the adjoint state).
 #include "lbm_adjoint.h"
 #include "lbm_kernels_impl.h"
 
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(NB) void k_adj_events(AdjArgs a) {
     if (so) {
         double s0 = 0.0, s1v = 0.0;
         int cnt = 0;
+#pragma unroll
         for (int i = 1; i < Q; i++) {
             int q[3];
             if (!step_in(p, i, g, q) || pnode(q[0], q[1], q[2], sn.X, D.R2, g)) continue;
@@ -252,6 +254,7 @@ __global__ __launch_bounds__(NB) void k_adj_kept(AdjArgs a) {
     if (in && !pnode(p[0], p[1], p[2], sn.X, D.R2, g) && !pnode(p[0], p[1], p[2], s1.X, D.R2, g)) {
         double s[2] = {0.0, 0.0};
         bool any = false;
+#pragma unroll
         for (int i = 1; i < Q; i++) {
             int q[3];
             if (!step_in(p, i, g, q)) continue;
@@ -466,8 +469,10 @@ __device__ __forceinline__ void node_finish(const NodeFwd<T> &f, const RepDesc &
 // streaming took it (a neighbour's Abar; the node's own reflected Abar for
 // links through a wall or into the sphere, whose moving-wall terms
 // k_adj_links adds), then the collision and node-local force adjoints.
+// FP32: held to 128 VGPRs (four waves per SIMD; a few values spill), which
+// hides more of the gathers' latency than the unconstrained 132.
 template <typename T>
-__global__ __launch_bounds__(NB) void k_adj_local(AdjArgs a) {
+__global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adj_local(AdjArgs a) {
     __shared__ double red[(NB / 64) * ADJ_PA];
     const RepDesc D = a.desc[0];
     const RepState sn = *a.stn;
@@ -546,16 +551,18 @@ __global__ __launch_bounds__(NB) void k_adj_local(AdjArgs a) {
 }
 
 // ============================================================ k_adj_links
-// One thread per box node, fluid at X^n with links into the sphere.  For a
-// link i: f_opp(i)(x) = f*_i(x) - 6 w_i rho_l (c_i . u_b), u_b = U + Omega x d
-// (d = x - X^n; c_i . (Omega x c_i) = 0), exchanged momentum
-// (2 f*_i - 6 w_i rho_l c_i . u_b) c_i with torque about X^n, bounce-back
-// mass flux, and the wetting-layer reaction -G rho_l w_i rho~_l'(x + c_i) c_i
-// on the sphere.  k_adj_local took the reflected Abar for f*_i (and left the
-// node's rebuilt forward values in the box array); the rest of
-// its adjoint (2 q, q = c_i . (Fbar + Tbar x d)) goes through the same
-// (linear) node adjoint here and is added to the node's outputs, together
-// with the density adjoint of the link terms and the sphere adjoints.
+// Two lanes per box node fluid at X^n with links into the sphere, one per
+// component.  For a link i: f_opp(i)(x) = f*_i(x) - 6 w_i rho_l (c_i . u_b),
+// u_b = U + Omega x d (d = x - X^n; c_i . (Omega x c_i) = 0), exchanged
+// momentum (2 f*_i - 6 w_i rho_l c_i . u_b) c_i with torque about X^n,
+// bounce-back mass flux, and the wetting-layer reaction
+// -G rho_l w_i rho~_l'(x + c_i) c_i on the sphere.  k_adj_local took the
+// reflected Abar for f*_i (and left the node's rebuilt forward values in the
+// box array); the rest of its adjoint (2 q, q = c_i . (Fbar + Tbar x d)) goes
+// through the same node adjoint here, which is linear: each lane applies it
+// to its component's share and the pair's sums are added to the node's
+// outputs, with the density adjoint of the link terms and the sphere
+// adjoints.
 template <typename T>
 __global__ __launch_bounds__(NB) void k_adj_links(AdjArgs a) {
     __shared__ double red[(NB / 64) * ADJ_PA];
@@ -571,7 +578,8 @@ __global__ __launch_bounds__(NB) void k_adj_links(AdjArgs a) {
     double acc[ADJ_PA];
 #pragma unroll
     for (int k = 0; k < ADJ_PA; k++) acc[k] = 0.0;
-    const int b = blockIdx.x * NB + threadIdx.x;
+    const int tid = blockIdx.x * NB + threadIdx.x;
+    const int b = tid >> 1, l = tid & 1;
     int bb[3], p[3];
     const bool in = b < S3 && bbox_pos(b, sn.org, Sx, g, bb, p);
     // links of a fluid node (the predicate combined as pnode combines it)
@@ -583,89 +591,92 @@ __global__ __launch_bounds__(NB) void k_adj_links(AdjArgs a) {
             for (int i = 1; i < Q; i++)
                 if (nbr_ok(nb, i) && pnode_nb(nb, i, D.R2)) lk |= 1u << i;
     }
-    if (lk) {
+    if (lk) {  // both lanes of the pair
         const int64_t n = lin(p, g);
         const Coef<T> cf = make_coef_dev<T>(D);
         // forward values of this node as k_adj_local rebuilt them
         const NodeFwd<T> f = static_cast<const NodeFwd<T> *>(a.nfw)[b];
-        {
-            const double d3[3] = {sepd(p[0] - sn.X[0], g.nx, g.wx), sepd(p[1] - sn.X[1], g.ny, g.wy),
-                                  sepd(p[2] - sn.X[2], g.nz, g.wz)};
-            double V[3], TxD[3];
-            cross3(sn.W, d3, V);
-            for (int q = 0; q < 3; q++) V[q] += sn.U[q];
-            cross3(ad.Tb, d3, TxD);
-            T rb[2], Fbv[2][3];
-            T ub[3] = {T(0), T(0), T(0)}, xb[3] = {T(0), T(0), T(0)};
-            double rlk[2] = {0.0, 0.0};
-#pragma unroll 1
-            for (int l = 0; l < 2; l++) {
-                T zl[16];
-                comp_noise(D, sn, n, l, cf, zl);
-                const T jc[3] = {l ? f.jl[1][0] : f.jl[0][0], l ? f.jl[1][1] : f.jl[0][1], l ? f.jl[1][2] : f.jl[0][2]};
-                const T Fc[3] = {l ? f.F[1][0] : f.F[0][0], l ? f.F[1][1] : f.F[0][1], l ? f.F[1][2] : f.F[0][2]};
-                const T rdl = l ? f.rd[1] : f.rd[0];
-                T fo[Q];
-                relax_tau1(T(D.rho0[l]), l ? T(-1) : T(1), rdl, jc, Fc, f.u, f.xid, zl, cf, fo);
-                const T Ar = A1[l * N + n];
-                const T Aj[3] = {A1[(2 + 3 * l) * N + n], A1[(3 + 3 * l) * N + n], A1[(4 + 3 * l) * N + n]};
-                const double rld = (double)(l ? f.rl[1] : f.rl[0]);
-                const double dMbl = l ? ad.dMb[1] : ad.dMb[0];
-                double rlkl = 0.0;
-                T dfp[Q];
+        const double d3[3] = {sepd(p[0] - sn.X[0], g.nx, g.wx), sepd(p[1] - sn.X[1], g.ny, g.wy),
+                              sepd(p[2] - sn.X[2], g.nz, g.wz)};
+        double V[3], TxD[3];
+        cross3(sn.W, d3, V);
+        for (int q = 0; q < 3; q++) V[q] += sn.U[q];
+        cross3(ad.Tb, d3, TxD);
+        T zl[16];
+        comp_noise(D, sn, n, l, cf, zl);
+        const T jc[3] = {l ? f.jl[1][0] : f.jl[0][0], l ? f.jl[1][1] : f.jl[0][1], l ? f.jl[1][2] : f.jl[0][2]};
+        const T Fc[3] = {l ? f.F[1][0] : f.F[0][0], l ? f.F[1][1] : f.F[0][1], l ? f.F[1][2] : f.F[0][2]};
+        const T rdl = l ? f.rd[1] : f.rd[0];
+        T fo[Q];
+        relax_tau1(T(l ? D.rho0[1] : D.rho0[0]), l ? T(-1) : T(1), rdl, jc, Fc, f.u, f.xid, zl, cf, fo);
+        const T Ar = A1[l * N + n];
+        const T Aj[3] = {A1[(2 + 3 * l) * N + n], A1[(3 + 3 * l) * N + n], A1[(4 + 3 * l) * N + n]};
+        const double rld = (double)(l ? f.rl[1] : f.rl[0]);
+        const double dMbl = l ? ad.dMb[1] : ad.dMb[0];
+        const double r0l = l ? D.rho0[1] : D.rho0[0];
+        double rlkl = 0.0;
+        T dfp[Q];
 #pragma unroll
-                for (int i = 0; i < Q; i++) dfp[i] = T(0);
+        for (int i = 0; i < Q; i++) dfp[i] = T(0);
 #pragma unroll 1
-                for (int i = 1; i < Q; i++) {
-                    if (!(f.link >> i & 1u)) continue;
-                    const double c3[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
-                    int q3[3];
-                    step_in(p, i, g, q3);
-                    const int bm = bbox_index(q3[0], q3[1], q3[2], sn.org, Sx, g);
-                    const double vo = a.vt[(1 - l) * S3 + bm];
-                    const double cu = c3[0] * V[0] + c3[1] * V[1] + c3[2] * V[2];
-                    const double qv = c3[0] * (ad.Fb[0] + TxD[0]) + c3[1] * (ad.Fb[1] + TxD[1]) +
-                                      c3[2] * (ad.Fb[2] + TxD[2]);
-                    const double fs = wgt(i) * D.rho0[l] + (double)fo[i];
-                    const double corr = 6.0 * wgt(i) * rld * cu;
-                    const double lpm = 2.0 * fs - corr;
-                    const double al = (double)Ar - (c3[0] * (double)Aj[0] + c3[1] * (double)Aj[1] +
-                                                    c3[2] * (double)Aj[2]);
-                    dfp[i] = T(2.0 * qv);
-                    const double corrb = -al - qv - dMbl;
-                    const double cub = 6.0 * wgt(i) * rld * corrb;
-                    const double flm = -D.G * rld * wgt(i) * vo;
-                    rlkl += 6.0 * wgt(i) * cu * corrb + D.G * wgt(i) * vo * qv;
-                    acc[0] += rld * wgt(i) * vo * qv;
-                    double cW[3], cT[3], dc[3];
-                    cross3(c3, sn.W, cW);
-                    cross3(c3, ad.Tb, cT);
-                    cross3(d3, c3, dc);
-                    for (int q = 0; q < 3; q++) {
-                        acc[4 + q] += cub * c3[q];
-                        acc[7 + q] += cub * dc[q];
-                        acc[10 + q] += -(cub * cW[q] + lpm * cT[q]) + flm * cT[q];
-                    }
-                }
-                T rbl, Fbl[3];
-                comp_adjoint(f, l, dfp, zl, cf, rbl, Fbl, ub, xb);
-                if (l) {
-                    rb[1] = rbl;
-                    rlk[1] = rlkl;
-                    for (int q = 0; q < 3; q++) Fbv[1][q] = Fbl[q];
-                } else {
-                    rb[0] = rbl;
-                    rlk[0] = rlkl;
-                    for (int q = 0; q < 3; q++) Fbv[0][q] = Fbl[q];
-                }
+        for (int i = 1; i < Q; i++) {
+            if (!(f.link >> i & 1u)) continue;
+            const double c3[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+            int q3[3];
+            step_in(p, i, g, q3);
+            const int bm = bbox_index(q3[0], q3[1], q3[2], sn.org, Sx, g);
+            const double vo = a.vt[(1 - l) * S3 + bm];
+            const double cu = c3[0] * V[0] + c3[1] * V[1] + c3[2] * V[2];
+            const double qv = c3[0] * (ad.Fb[0] + TxD[0]) + c3[1] * (ad.Fb[1] + TxD[1]) +
+                              c3[2] * (ad.Fb[2] + TxD[2]);
+            const double fs = wgt(i) * r0l + (double)fo[i];
+            const double corr = 6.0 * wgt(i) * rld * cu;
+            const double lpm = 2.0 * fs - corr;
+            const double al = (double)Ar - (c3[0] * (double)Aj[0] + c3[1] * (double)Aj[1] +
+                                            c3[2] * (double)Aj[2]);
+            dfp[i] = T(2.0 * qv);
+            const double corrb = -al - qv - dMbl;
+            const double cub = 6.0 * wgt(i) * rld * corrb;
+            const double flm = -D.G * rld * wgt(i) * vo;
+            rlkl += 6.0 * wgt(i) * cu * corrb + D.G * wgt(i) * vo * qv;
+            acc[0] += rld * wgt(i) * vo * qv;
+            double cW[3], cT[3], dc[3];
+            cross3(c3, sn.W, cW);
+            cross3(c3, ad.Tb, cT);
+            cross3(d3, c3, dc);
+            for (int q = 0; q < 3; q++) {
+                acc[4 + q] += cub * c3[q];
+                acc[7 + q] += cub * dc[q];
+                acc[10 + q] += -(cub * cW[q] + lpm * cT[q]) + flm * cT[q];
             }
-            T jb[3];
-            node_finish(f, D, cf, rb, Fbv, ub, xb, jb, acc);
-            for (int l = 0; l < 2; l++) {
-                A0[l * N + n] = T((double)A0[l * N + n] + (double)rb[l] + rlk[l]);
+        }
+        T rbl, Fbl[3];
+        T ub[3] = {T(0), T(0), T(0)}, xb[3] = {T(0), T(0), T(0)};
+        comp_adjoint(f, l, dfp, zl, cf, rbl, Fbl, ub, xb);
+        // this lane's share of the node adjoint (the other component's inputs are zero)
+        T rb[2] = {l ? T(0) : rbl, l ? rbl : T(0)};
+        T Fbv[2][3];
+        for (int q = 0; q < 3; q++) {
+            Fbv[0][q] = l ? T(0) : Fbl[q];
+            Fbv[1][q] = l ? Fbl[q] : T(0);
+        }
+        T jb[3];
+        node_finish(f, D, cf, rb, Fbv, ub, xb, jb, acc);
+        double out[13];
+        out[0] = (double)rb[0] + (l ? 0.0 : rlkl);
+        out[1] = (double)rb[1] + (l ? rlkl : 0.0);
+        for (int q = 0; q < 3; q++) {
+            out[2 + q] = (double)jb[q];
+            out[5 + q] = (double)Fbv[0][q];
+            out[8 + q] = (double)Fbv[1][q];
+        }
+        for (int k = 0; k < 11; k++) out[k] += __shfl_xor(out[k], 1);
+        if (l == 0) {
+            for (int c = 0; c < 2; c++) {
+                A0[c * N + n] = T((double)A0[c * N + n] + out[c]);
                 for (int q = 0; q < 3; q++) {
-                    A0[(2 + 3 * l + q) * N + n] += jb[q];
-                    Fo[(3 * l + q) * N + n] += Fbv[l][q];
+                    A0[(2 + 3 * c + q) * N + n] += T(out[2 + q]);
+                    Fo[(3 * c + q) * N + n] += T(out[5 + 3 * c + q]);
                 }
             }
         }
@@ -803,6 +814,7 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
         const bool solid = near && solid_at(p[0], p[1], p[2], D, sn.org, sn.X, g, bs);
         const T G = T(D.G);
         T s[2] = {T(0), T(0)};
+#pragma unroll
         for (int i = 1; i < Q; i++) {
             const int c3[3] = {cx(i), cy(i), cz(i)};
             int pl[3];
@@ -859,6 +871,43 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
     }
 }
 
+// Fixed-order sums (one workgroup of NB threads; the order depends on the
+// partial indices only) of the node-kernel, link, wall-mirror and chain
+// partials into the adjoint state: G, a_f, U, Omega, X adjoints; the
+// density-adjoint sum of the reversed state for the next mass correction;
+// Delta rho.  Resets the completion counter.
+__device__ __forceinline__ void adj_sums(const AdjArgs &a, double *red) {
+    const int t = threadIdx.x;
+    double acc[18];
+#pragma unroll
+    for (int k = 0; k < 18; k++) acc[k] = 0.0;
+    for (int w = t; w < a.nwg; w += NB) {
+        for (int k = 0; k < ADJ_PA; k++) acc[k] += a.partA[(int64_t)w * ADJ_PA + k];
+        for (int k = 0; k < ADJ_PB; k++) acc[ADJ_PA + k] += a.partB[(int64_t)w * ADJ_PB + k];
+    }
+    for (int w = t; w < a.nmw; w += NB)
+        for (int k = 0; k < 2; k++) acc[15 + k] += a.partM[(int64_t)w * PART + k];
+    for (int w = t; w < 2 * a.nbw; w += NB)
+        for (int k = 0; k < ADJ_PA; k++) acc[k] += a.partL[(int64_t)w * PART + k];
+    for (int w = t; w < a.nbw; w += NB)
+        for (int k = 0; k < ADJ_PC; k++) acc[15 + k] += a.partC[(int64_t)w * PART + k];
+    block_sum<NB, 18>(acc, red);
+    if (t != 0) return;
+    AdjState *o = a.adj;
+    o->done = 0u;
+    o->grad[3] += acc[0];
+    for (int q = 0; q < 3; q++) {
+        o->afb[q] += acc[1 + q];
+        o->Ub[q] += acc[4 + q];
+        o->Wb[q] += acc[7 + q];
+        o->Xb[q] += acc[10 + q];
+    }
+    o->dsum[0] = acc[13] + acc[15];
+    o->dsum[1] = acc[14] + acc[16];
+    o->grad[4] += acc[17];
+}
+
+
 // ============================================================= k_adj_chain
 // One thread per box node.  Wetting layer: rho~_l(s) = mean over fluid
 // neighbours of rho_l +/- Delta rho on particle nodes s, so each fluid
@@ -868,6 +917,7 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
 template <typename T>
 __global__ __launch_bounds__(NB) void k_adj_chain(AdjArgs a) {
     __shared__ double red[(NB / 64) * ADJ_PC];
+    __shared__ double red2[(NB / 64) * 18];
     const RepDesc D = a.desc[0];
     const RepState sn = *a.stn;
     const Geo g = geo_of(D);
@@ -883,6 +933,7 @@ __global__ __launch_bounds__(NB) void k_adj_chain(AdjArgs a) {
     } else if (in) {
         double s[2] = {0.0, 0.0};
         bool any = false;
+#pragma unroll
         for (int i = 1; i < Q; i++) {
             int q[3];
             if (!step_in(p, i, g, q)) continue;
@@ -905,41 +956,15 @@ __global__ __launch_bounds__(NB) void k_adj_chain(AdjArgs a) {
     block_sum<NB, ADJ_PC>(acc, red);
     if (threadIdx.x == 0)
         for (int k = 0; k < ADJ_PC; k++) a.partC[(int64_t)blockIdx.x * PART + k] = acc[k];
-}
-
-// =============================================================== k_adj_sum
-// One workgroup: fixed-order sums of the node-kernel and chain partials into
-// the adjoint state (G, a_f, U, Omega, X adjoints; the density-adjoint sum
-// of the reversed state for the next mass correction; Delta rho).
-__global__ __launch_bounds__(ADJ_BOX) void k_adj_sum(AdjArgs a) {
-    __shared__ double red[(ADJ_BOX / 64) * 18];
-    const int t = threadIdx.x;
-    double acc[18];
-#pragma unroll
-    for (int k = 0; k < 18; k++) acc[k] = 0.0;
-    for (int w = t; w < a.nwg; w += ADJ_BOX) {
-        for (int k = 0; k < ADJ_PA; k++) acc[k] += a.partA[(int64_t)w * ADJ_PA + k];
-        for (int k = 0; k < ADJ_PB; k++) acc[ADJ_PA + k] += a.partB[(int64_t)w * ADJ_PB + k];
-    }
-    for (int w = t; w < a.nmw; w += ADJ_BOX)
-        for (int k = 0; k < 2; k++) acc[15 + k] += a.partM[(int64_t)w * PART + k];
-    for (int w = t; w < a.nbw; w += ADJ_BOX) {
-        for (int k = 0; k < ADJ_PA; k++) acc[k] += a.partL[(int64_t)w * PART + k];
-        for (int k = 0; k < ADJ_PC; k++) acc[15 + k] += a.partC[(int64_t)w * PART + k];
-    }
-    block_sum<ADJ_BOX, 18>(acc, red);
-    if (t != 0) return;
-    AdjState *o = a.adj;
-    o->grad[3] += acc[0];
-    for (int q = 0; q < 3; q++) {
-        o->afb[q] += acc[1 + q];
-        o->Ub[q] += acc[4 + q];
-        o->Wb[q] += acc[7 + q];
-        o->Xb[q] += acc[10 + q];
-    }
-    o->dsum[0] = acc[13] + acc[15];
-    o->dsum[1] = acc[14] + acc[16];
-    o->grad[4] += acc[17];
+    // the last workgroup to finish sums every partial of the reversed step
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&a.adj->done, 1u) == (unsigned)(a.nbw - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    adj_sums(a, red2);
 }
 
 template <typename S, typename T>
@@ -961,11 +986,10 @@ hipError_t launch_step_t(const AdjArgs &a, hipStream_t s, hipEvent_t e0, hipEven
         const hipError_t e = hipEventRecord(e1, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_adj_links<T>), dim3(a.nbw), dim3(NB), 0, s, a);
+    hipLaunchKernelGGL((k_adj_links<T>), dim3(2 * a.nbw), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_gather<T>), dim3(a.nwg), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_mirror<T>), dim3(a.nmw), dim3(NB), 0, s, a);
     hipLaunchKernelGGL((k_adj_chain<T>), dim3(a.nbw), dim3(NB), 0, s, a);
-    hipLaunchKernelGGL(k_adj_sum, dim3(1), dim3(ADJ_BOX), 0, s, a);
     return hipGetLastError();
 }
 

@@ -449,7 +449,7 @@ AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     A.partB = take(sizeof(double) * ADJ_PB * A.nwg);
     A.partE = take(sizeof(double) * PART * A.nbw);
     A.partC = take(sizeof(double) * PART * A.nbw);
-    A.partL = take(sizeof(double) * PART * A.nbw);
+    A.partL = take(sizeof(double) * PART * 2 * A.nbw);
     A.partM = take(sizeof(double) * PART * A.nmw);
     A.adj = take(sizeof(AdjState));
     A.total = o;
