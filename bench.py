@@ -278,8 +278,8 @@ def main():
                          "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (the hot path is one GPU's share); "
-              "multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU (the hot path is one GPU's share); "
+              "a multi-GPU run is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
