@@ -16,7 +16,12 @@ never against a re-typed copy of the oracle's own formula:
   * the textbook series of Poiseuille flow in a square duct;
   * invariants: per-component mass with a moving sphere and cover/uncover
     events, total momentum of fluid + particle, zero force on a co-moving
-    sphere.
+    sphere;
+  * brute force: an independent dense-matrix, population-space restatement
+    of the whole step (tests/brute_force.py) on a tiny walled channel with a
+    moving sphere, which planted mistakes in the oracle fail;
+  * the adjoint against central differences of the forward step and the
+    linear-response limit dJ/dg_z = J/g_z.
 """
 import os
 import shutil
@@ -489,3 +494,81 @@ def test_adjoint_rejects_unsupported(oracle_lib):
     sim = oracle_lib.OracleSim(dict(_ADJ_CASE, radius=0.0))
     with pytest.raises(ValueError):
         sim.adjoint(2)
+
+
+def test_brute_force_step(oracle_lib):
+    """20 steps of the oracle against an independent brute-force restatement
+    (tests/brute_force.py): dense 19 x 19 mode matrix and its inverse
+    diag(w) M^T diag(1/b), Guo source and f_eq in population space, distinct
+    relaxation rates for every group, noise, Shan-Chen forces with wall
+    mirrors and a wetting layer, naive per-link loops for the moving sphere
+    (momentum exchange, torque), cover/uncover and the mass correction, on a
+    6 x 6 x 8 walled channel with a small sphere in motion."""
+    from brute_force import BruteForce
+    p = dict(oracle_lib.DEFAULTS)
+    p.update(nx=6, ny=6, nz=8, walls=3, init_amp=1e-3, G=1.5, tau_shear=0.8, tau_bulk=1.1,
+             tau_mom=0.9, tau_ghost=1.3, kT=1e-4, seed=11, g=(0.0, 0.0, 2e-4), radius=1.3,
+             rho_p=2.0, wet_drho=0.2, X0=(2.6, 2.4, 3.7), U0=(0.03, -0.02, 0.09),
+             W0=(0.01, 0.02, 0.03))
+    sim = oracle_lib.OracleSim(p)
+    f0 = sim.populations()
+    bf = BruteForce(dict(p, M0=float(f0.sum())), f0, sim.particle(), sim.normals)
+    for _ in range(20):
+        sim.step(1)
+        bf.step()
+    f = sim.populations()
+    assert np.abs(f - bf.f).max() <= 1e-13 * np.abs(f).max()
+    P = sim.particle()
+    assert (P["n_covered"], P["n_uncovered"]) == (bf.n_cov, bf.n_unc)
+    assert bf.n_cov > 0 and bf.n_unc > 0
+    for key, v in (("X", bf.X), ("U", bf.U), ("W", bf.Wv), ("F", bf.F), ("T", bf.T)):
+        assert np.abs(P[key] - v).max() <= 1e-12 * max(np.abs(P[key]).max(), 1e-300), key
+
+
+_PLANTS = {
+    # Guo term of mode 5 with the wrong sign of u.F
+    "guo": ("phi[5] = 2.0 * (3.0 * u[0] * Fl[0] - uF);", "phi[5] = 2.0 * (3.0 * u[0] * Fl[0] + uF);"),
+    # wetting offset added to component B instead of subtracted
+    "wetting": ("s->rt[N + n] = sum[1] / cnt - p->wet_drho;", "s->rt[N + n] = sum[1] / cnt + p->wet_drho;"),
+    # link torque with the operands of the cross product swapped
+    "torque": ("                        cross(r, lp, t);", "                        cross(lp, r, t);"),
+}
+
+
+@pytest.mark.parametrize("plant", sorted(_PLANTS))
+def test_brute_force_detects_planted_mistake(oracle_lib, plant, tmp_path):
+    """The brute-force pin is not vacuous: an oracle built with one planted
+    mistake (a sign, an operand order) no longer matches it."""
+    from brute_force import BruteForce
+    src = open(os.path.join(os.path.dirname(oracle_lib.LIB_PATH), "lbm_oracle.c")).read()
+    old, new = _PLANTS[plant]
+    assert src.count(old) == 1
+    path = tmp_path / "planted.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "libplanted.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I" + os.path.dirname(oracle_lib.LIB_PATH), "-o", str(lib), str(path), "-lm"],
+                   check=True)
+    saved = oracle_lib._lib
+    try:
+        oracle_lib._lib = None
+        keep = oracle_lib.LIB_PATH
+        oracle_lib.LIB_PATH = str(lib)
+        p = dict(oracle_lib.DEFAULTS)
+        p.update(nx=6, ny=6, nz=8, walls=3, init_amp=1e-3, G=1.5, tau_shear=0.8, tau_bulk=1.1,
+                 tau_mom=0.9, tau_ghost=1.3, kT=1e-4, seed=11, g=(0.0, 0.0, 2e-4), radius=1.3,
+                 rho_p=2.0, wet_drho=0.2, X0=(2.6, 2.4, 3.7), U0=(0.03, -0.02, 0.09),
+                 W0=(0.01, 0.02, 0.03))
+        sim = oracle_lib.OracleSim(p)
+        f0 = sim.populations()
+        bf = BruteForce(dict(p, M0=float(f0.sum())), f0, sim.particle(), sim.normals)
+        for _ in range(10):
+            sim.step(1)
+            bf.step()
+        f = sim.populations()
+        err = np.abs(f - bf.f).max() / np.abs(f).max()
+        assert not err <= 1e-13
+        del sim
+    finally:
+        oracle_lib.LIB_PATH = keep
+        oracle_lib._lib = saved
