@@ -168,6 +168,40 @@ def adjoint_bench(torch, args, steps, segment=50):
     print(json.dumps(out), flush=True)
 
 
+def friction_study(torch, steps=12000, tail=1000):
+    """Deterministic confinement friction (kT = 0): terminal settling
+    velocity of spheres of several d/L in the square channel, one replica per
+    radius in one context, and the friction factor relative to Stokes,
+    c_m = F_ext / (3 pi eta d U), F_ext = V (rho_p - rho_tot) g (Sec. 3 eq. fp),
+    eta = rho_tot nu, nu = (tau - 1/2) / 3."""
+    import math
+    from paper_1909_01092_amd import workloads as w
+    from paper_1909_01092_amd.sim import Simulation
+    reps = w.friction(steps_cap=steps)
+    sim = Simulation(reps, precision="fp32", device="cuda:0", stream=torch.cuda.Stream())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    el = time.perf_counter() - t0
+    rows = []
+    for r, q in enumerate(reps):
+        u = sim.u_series(r)[:, 2]
+        U, Uprev = u[-tail:].mean(), u[-2 * tail:-tail].mean()
+        R = q["radius"]
+        rho = q["rho0"][0] + q["rho0"][1]
+        Fext = 4.0 / 3.0 * math.pi * R ** 3 * (q["rho_p"] - rho) * q["g"][2]
+        eta = rho * (q["tau_shear"] - 0.5) / 3.0
+        rows.append({"R": R, "d_over_L": 2 * R / q["nx"], "U": float(U),
+                     "drift": float(abs(U - Uprev) / abs(U)), "c_m": float(Fext / (3 * math.pi * eta * 2 * R * U)),
+                     "Re": float(abs(U) * 2 * R * 3.0 / (q["tau_shear"] - 0.5))})
+    nodes = sum(q["nx"] * q["ny"] * q["nz"] for q in reps)
+    sim.close()
+    return {"study": "confinement friction, kT = 0", "channel": f"{w.FRICTION_L}x{w.FRICTION_L}x{w.FRICTION_LZ}",
+            "steps": steps, "mean_over_last": tail, "seconds": round(el, 3),
+            "MLUPS": round(nodes * steps / el / 1e6, 1), "rows": rows}
+
+
 def langevin_stats(sim, reps, steps, skip):
     """Per-replica mean and variance of the particle velocity U_z over the
     last steps - skip recorded steps, grouped by lattice size, with the
@@ -273,6 +307,9 @@ def main():
                     help="instead of timing: run the large workload for STEPS steps in FP16 and in "
                          "FP32 storage on the same noise and report the FP16 error of the mean "
                          "velocity profile and of the particle velocity variance")
+    ap.add_argument("--study", default="", choices=["", "friction"],
+                    help="instead of timing: run a physics study and print its table (friction: "
+                         "deterministic confinement friction c_m(d/L) at kT = 0)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the step: time a plain device copy of this many MiB "
                          "(calibrates the HBM byte counters)")
@@ -288,6 +325,9 @@ def main():
         return
     if args.fp16_error:
         fp16_error(torch, args.fp16_error)
+        return
+    if args.study == "friction":
+        print(json.dumps(friction_study(torch, steps=args.steps or 12000)), flush=True)
         return
     if args.workload == "adjoint":
         adjoint_bench(torch, args, args.steps or 1000)

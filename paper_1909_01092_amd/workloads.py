@@ -62,3 +62,16 @@ ADJOINT = channel(48, 192, kT=1e-5, radius=6.0, g=(0.0, 0.0, 5e-5), seed=3)
 LARGE = channel(192, 192, kT=1e-4, radius=16.0, g=(0.0, 0.0, 1e-4), seed=5)
 LARGE["nz"] = 1024
 LARGE = full(dict(LARGE, X0=None))
+
+# deterministic confinement friction (kT = 0): one replica per sphere radius
+# in a 32 x 32 x 128 channel, uniform initial densities, g small enough for
+# creeping flow (Re = U d / nu below 2e-3)
+FRICTION_L, FRICTION_LZ = 32, 128
+FRICTION_RADII = (2.5, 3.5, 5.0, 6.5, 8.0, 10.0)
+FRICTION_G = 1e-6
+
+
+def friction(steps_cap: int = 16384) -> list:
+    return [channel(FRICTION_L, FRICTION_LZ, kT=0.0, init_amp=0.0, radius=R, g=(0.0, 0.0, FRICTION_G),
+                    seed=0, replica=k, series_cap=steps_cap)
+            for k, R in enumerate(FRICTION_RADII)]

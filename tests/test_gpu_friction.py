@@ -1,0 +1,73 @@
+"""Deterministic confinement friction at kT = 0: a sphere settling in the
+square channel (Sec. 3, the friction-coefficient figure) on the GPU path.
+
+c_m = F_ext / (3 pi eta d U) against d / L, one replica per radius:
+  * terminal velocity reached (the last two 1000-step means agree to 1e-2;
+    the rest is the staircase sphere's drag changing as it slides over the
+    lattice);
+  * c_m > 1 and increasing with d / L, with (c_m - 1) / (d / L) increasing
+    too (confinement grows faster than linearly);
+  * at the smallest d / L the first-order coefficient (c_m - 1) / (d / L) is
+    O(1) (between 0.5 and 4), so c_m -> 1 as d / L -> 0.  The coefficient is
+    not pinned tighter: the hydrodynamic radius of a bounce-back sphere
+    differs from its nominal radius by a fraction of a node, 10% of the drag
+    at R = 2.5, and the container holds no comparison data.
+Parity: the largest sphere's channel against the FP64 oracle.
+"""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from paper_1909_01092_amd import workloads
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_01092_amd.sim import Simulation
+    return Simulation
+
+
+def test_friction_channel_parity(Sim):
+    p = workloads.friction()[-1]
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.step(20)
+    ref.step(20)
+    f, fr = sim.populations(), ref.populations()
+    err = np.abs(f - fr).max() / np.abs(fr).max()
+    print(f"friction channel R = {p['radius']}: 20 steps, rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+    # U is still O(1e-6) here, a sum of link momenta of O(1e-2): cancellation
+    # leaves about 1e-16 absolute (1e-10 relative) from the summation order
+    pg, po = sim.particle_state(), ref.particle()
+    assert np.abs(pg["U"] - po["U"]).max() <= 1e-9 * np.abs(po["U"]).max()
+
+
+def test_confinement_friction_trend(Sim):
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    out = bench.friction_study(torch, steps=12000)
+    for r in out["rows"]:
+        print(f"  d/L {r['d_over_L']:.3f}  U {r['U']:.4e}  c_m {r['c_m']:.3f}  Re {r['Re']:.1e}  "
+              f"drift {r['drift']:.1e}", flush=True)
+    rows = out["rows"]
+    dl = np.array([r["d_over_L"] for r in rows])
+    cm = np.array([r["c_m"] for r in rows])
+    assert all(r["drift"] < 1e-2 for r in rows)
+    assert all(r["Re"] < 1e-2 for r in rows)
+    assert cm[0] > 1.0
+    assert np.all(np.diff(cm) > 0)
+    slope = (cm - 1.0) / dl
+    assert np.all(np.diff(slope) > 0)
+    assert 0.5 < slope[0] < 4.0
