@@ -1,6 +1,6 @@
 """Throughput of the fluctuating two-component D3Q19 + sphere step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|ensemble|large|parity|adjoint]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|ensemble|large|paper|parity|adjoint]
 
 Prints ONE JSON line: MLUPS (replica node updates per second / 1e6, both
 components of a node counted once) for the chosen workload with all inputs
@@ -52,6 +52,9 @@ def workload(name):
     if name == "large":
         return ([w.LARGE], "fp16", "large single run 192x192x1024, FP16 relative deviations, "
                 "R=16, kT=1e-4, g=1e-4")
+    if name == "paper":
+        return ([w.paper_box()], "fp32", "paper geometry: closed 60x60x900 box, rho_A/rho_B = 2.21/0.09, "
+                "G = 1.5, R = 8, kT = 1e-4, g = 5e-6, FP32 deviations")
     if name == "parity":
         return ([w.PARITY_SMALL], "fp64", "parity channel 24x24x48, FP64, R=4, kT=1e-5")
     raise SystemExit(f"unknown workload {name}")

@@ -75,3 +75,18 @@ def friction(steps_cap: int = 16384) -> list:
     return [channel(FRICTION_L, FRICTION_LZ, kT=0.0, init_amp=0.0, radius=R, g=(0.0, 0.0, FRICTION_G),
                     seed=0, replica=k, series_cap=steps_cap)
             for k, R in enumerate(FRICTION_RADII)]
+
+# the paper's own setup (Sec. 3): closed 60 x 60 x 900 box (walls on every
+# axis, neutral), rho_A = 2.21, rho_B = 0.09, G = 1.5 (G rho_tot = 3.45, the
+# A-rich side of the miscibility gap, far from its spinodal), rho_p = 2 rho_tot;
+# sphere of d / L = 0.27 low in the box, settling along +z
+PAPER_RHO0 = (2.21, 0.09)
+
+
+def paper_box(n: int = 60, nz: int = 900, radius: float = 8.0, kT: float = 1e-4, g: float = 5e-6,
+              steps_cap: int = 4096) -> dict:
+    rho_tot = PAPER_RHO0[0] + PAPER_RHO0[1]
+    return full(dict(nx=n, ny=n, nz=nz, walls=7, rho0=PAPER_RHO0, init_amp=1e-3, G=1.5,
+                     rho_p=2.0 * rho_tot, kT=kT, radius=radius, g=(0.0, 0.0, g), seed=9,
+                     X0=((n - 1) / 2.0, (n - 1) / 2.0, min(nz / 4.0, 3.0 * radius + 4.0)),
+                     series_cap=steps_cap))
