@@ -31,6 +31,13 @@ WALLS = workloads.full(dict(nx=18, ny=14, nz=23, walls=7, rho0=(0.95, 0.05), ini
                             rho_p=1.5, wet_drho=-0.2, X0=(8.7, 6.6, 11.2), U0=(0.0, 0.01, 0.04),
                             W0=(0.0, 0.0, 0.02), noise_diffusive=0))
 
+# fully periodic box; the sphere sits at a corner, so its bounding box wraps
+# across two periodic faces, and it crosses the x face during the window
+PERIODIC = workloads.full(dict(nx=14, ny=14, nz=14, walls=0, rho0=(0.95, 0.05), init_amp=1e-3, G=1.5,
+                               kT=1e-5, seed=8, g=(0.0, 0.0, 5e-5), force_mode=0, radius=2.6,
+                               rho_p=2.0, wet_drho=-0.1, X0=(0.1, 13.2, 6.5), U0=(-0.05, 0.04, 0.05),
+                               W0=(0.02, -0.01, 0.01)))
+
 
 @pytest.fixture(scope="module")
 def Sim():
@@ -51,9 +58,9 @@ def _report(what, J, grad, Jo, go):
         print(f"  grad[{k}] {grad[k]: .12e} oracle {go[k]: .12e}", flush=True)
 
 
-@pytest.mark.parametrize("case,steps", [("EVENTS", 30), ("WALLS", 40)])
+@pytest.mark.parametrize("case,steps", [("EVENTS", 30), ("WALLS", 40), ("PERIODIC", 30)])
 def test_adjoint_fp64_matches_oracle(Sim, case, steps):
-    p = {"EVENTS": EVENTS, "WALLS": WALLS}[case]
+    p = {"EVENTS": EVENTS, "WALLS": WALLS, "PERIODIC": PERIODIC}[case]
     print(f"case {case} steps {steps}", flush=True)
     Jo, go = _oracle(p, steps)
     sim = Sim(p, "fp64")
@@ -62,9 +69,11 @@ def test_adjoint_fp64_matches_oracle(Sim, case, steps):
     assert abs(J - Jo) <= 1e-12 * abs(Jo)
     for k in range(5):
         assert abs(grad[k] - go[k]) <= 1e-9 * abs(go[k]) + 1e-14, (k, grad[k], go[k])
-    if case == "EVENTS":
+    if case in ("EVENTS", "PERIODIC"):
         st = sim.particle_state()
         assert st["n_covered"] > 0 and st["n_uncovered"] > 0
+    if case == "PERIODIC":
+        assert sim.particle_state()["X"][0] > 7.0  # wrapped across the x face
 
 
 def test_adjoint_fp32_matches_oracle(Sim):
