@@ -222,9 +222,10 @@ int lbm_step_bytes(lbm_ctx *c, double *bytes);
  * Requirements (else LBM_EINVAL): one replica, every relaxation time 1, a
  * sphere.  dev_adj: caller-owned device buffer, 256-byte aligned, of at
  * least lbm_adjoint_bytes(c, nsteps, segment) bytes (LBM_ENOMEM otherwise);
- * the library keeps no reference to it after the call.  On return the
+ * the library keeps no reference to it after the call.  On success the
  * context holds the state after the nsteps steps, as lbm_step(c, nsteps)
- * leaves it.  LBM_EUNSTABLE if the run is or goes unstable.  Synchronises
+ * leaves it; after LBM_EDEVICE it may hold any state the call passed
+ * through (restore a checkpoint taken before the call).  LBM_EUNSTABLE if the run is or goes unstable.  Synchronises
  * the context stream.  While lbm_timing is enabled, the launches this call
  * times (lbm_timing_read) are those of the adjoint's node kernel, one per
  * reversed step; its forward sweep and replays run untimed. */
