@@ -205,6 +205,72 @@ def friction_study(torch, steps=12000, tail=1000):
             "MLUPS": round(nodes * steps / el / 1e6, 1), "rows": rows}
 
 
+def interface_height(rho, X, clear):
+    """Height of the flat A|B interface far from the sphere: the zero of the
+    composition rho_A - rho_B averaged over the (x, y) columns farther than
+    `clear` from the sphere's axis, by linear interpolation between planes
+    (A below, B above)."""
+    import numpy as np
+    nz, ny, nx = rho.shape[1:]
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    far = np.hypot(xx - X[0], yy - X[1]) > clear
+    phi = (rho[0] - rho[1])[:, far].mean(1)
+    k = np.where((phi[:-1] > 0) & (phi[1:] <= 0))[0]
+    if len(k) != 1:
+        return float("nan")
+    k = int(k[0])
+    return k + phi[k] / (phi[k] - phi[k + 1])
+
+
+def wetting_study(torch, steps=30000, tail=10000, every=500):
+    """Contact angle of the wetting layer against Delta rho.  A sphere free to
+    move (no noise, no driving) at a flat interface between the two demixed
+    phases settles where the interface meets its surface at the contact
+    angle theta; with the A phase below, cos theta_A = (z_i - Z) / R (Young's
+    condition on a sphere, the interface staying flat).  Z and the far-field
+    interface height z_i are averaged over the last `tail` steps (sampled
+    every `every` steps): the staircase sphere keeps moving by a fraction of
+    a node.  The paper's three wettabilities (Sec. 3: theta = 120.5, 90,
+    55 degrees, measured in the majority phase A) are then read off by
+    linear interpolation."""
+    import math
+    import numpy as np
+    from paper_1909_01092_amd import workloads as w
+    from paper_1909_01092_amd.sim import Simulation
+    reps = w.wetting()
+    sim = Simulation(reps, precision="fp32", device="cuda:0", stream=torch.cuda.Stream())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps - tail)
+    h = [[] for _ in reps]
+    for _ in range(tail // every):
+        sim.step(every)
+        for r, q in enumerate(reps):
+            X = sim.particle_state(r)["X"]
+            rho, _ = sim.fields(r)
+            h[r].append(interface_height(rho, X, q["radius"] + 8.0) - X[2])
+    sim.sync()
+    el = time.perf_counter() - t0
+    rows = []
+    for r, q in enumerate(reps):
+        d = np.array(h[r])
+        c = float(d.mean() / q["radius"])
+        rows.append({"drho": q["wet_drho"], "zi_minus_Z": float(d.mean()), "spread": float(d.std()),
+                     "cos_theta": c, "theta_deg": math.degrees(math.acos(max(-1.0, min(1.0, c))))})
+    cos = np.array([x["cos_theta"] for x in rows])
+    drho = np.array([x["drho"] for x in rows])
+    calib = {}
+    if np.all(np.diff(cos) > 0):
+        for th in (120.5, 90.0, 55.0):
+            calib[f"{th:g}"] = float(np.interp(math.cos(math.radians(th)), cos, drho))
+    nodes = sum(q["nx"] * q["ny"] * q["nz"] for q in reps)
+    sim.close()
+    return {"study": "contact angle of the wetting layer, kT = 0",
+            "box": f"{w.WETTING_N}^3 closed, R = {w.WETTING_R:g}, rho {w.PAPER_RHO0}",
+            "steps": steps, "averaged_over_last": tail, "seconds": round(el, 3),
+            "MLUPS": round(nodes * steps / el / 1e6, 1), "rows": rows, "drho_for_theta": calib}
+
+
 def langevin_stats(sim, reps, steps, skip):
     """Per-replica mean and variance of the particle velocity U_z over the
     last steps - skip recorded steps, grouped by lattice size, with the
@@ -310,9 +376,10 @@ def main():
                     help="instead of timing: run the large workload for STEPS steps in FP16 and in "
                          "FP32 storage on the same noise and report the FP16 error of the mean "
                          "velocity profile and of the particle velocity variance")
-    ap.add_argument("--study", default="", choices=["", "friction"],
+    ap.add_argument("--study", default="", choices=["", "friction", "wetting"],
                     help="instead of timing: run a physics study and print its table (friction: "
-                         "deterministic confinement friction c_m(d/L) at kT = 0)")
+                         "deterministic confinement friction c_m(d/L) at kT = 0; wetting: contact "
+                         "angle against Delta rho of a sphere at a flat interface)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the step: time a plain device copy of this many MiB "
                          "(calibrates the HBM byte counters)")
@@ -331,6 +398,9 @@ def main():
         return
     if args.study == "friction":
         print(json.dumps(friction_study(torch, steps=args.steps or 12000)), flush=True)
+        return
+    if args.study == "wetting":
+        print(json.dumps(wetting_study(torch, steps=args.steps or 30000)), flush=True)
         return
     if args.workload == "adjoint":
         adjoint_bench(torch, args, args.steps or 1000)

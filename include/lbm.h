@@ -92,7 +92,10 @@ typedef struct lbm_params {
     int32_t noise_diffusive;   /* 1: noise on the species-momentum (diffusion) mode       */
     int32_t fixed_velocity;    /* 1: sphere moves with U0, W0 (prescribed)                */
     int32_t series_cap;        /* length of the per-step U ring buffer (>= 1)             */
-    int32_t reserved;
+    int32_t init_split;        /* 0: every node starts from rho0; k in [1, nz): nodes with */
+                               /* z >= k start from the swapped pair (rho0[1], rho0[0]),   */
+                               /* i.e. the other phase of a demixed mixture, which puts a  */
+                               /* flat A|B interface at z = k - 1/2                        */
 } lbm_params;
 
 /* Sphere state after the last completed step n. */
@@ -123,8 +126,9 @@ int lbm_workspace_bytes(const lbm_params *p, int32_t n_replicas, int32_t precisi
                         size_t *bytes);
 
 /* Validate, lay out the workspace, write the initial state (densities
- * rho0_l + init_amp (2u - 1) from Philox counter (node, 0, 0, 1), fluid at
- * rest) and return a context.  dev_ws: device pointer, 256-byte aligned. */
+ * rho0_l + init_amp (2u - 1) from Philox counter (node, 0, 0, 1), with rho0
+ * swapped on the planes z >= init_split when init_split > 0; fluid at rest)
+ * and return a context.  dev_ws: device pointer, 256-byte aligned. */
 int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision, void *dev_ws,
              size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 

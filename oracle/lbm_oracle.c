@@ -265,8 +265,11 @@ orc_sim *orc_create(const orc_params *p) {
                 if (s->solid[n]) continue;
                 uint32_t ctr[4] = {(uint32_t)n, 0u, 0u, 1u}, w[4];
                 orc_philox4x32_10(ctr, key, w);
+                /* a demixed start: the planes above the split hold the other phase */
+                const int swap = p->init_split > 0 && z >= p->init_split;
                 for (int l = 0; l < 2; l++) {
-                    double r = p->rho0[l] + p->init_amp * (2.0 * unit_open(w[l]) - 1.0);
+                    double base = swap ? p->rho0[1 - l] : p->rho0[l];
+                    double r = base + p->init_amp * (2.0 * unit_open(w[l]) - 1.0);
                     for (int i = 0; i < Q; i++) s->f[((int64_t)l * Q + i) * N + n] = s->W[i] * r;
                     s->M_fluid0 += r;
                 }

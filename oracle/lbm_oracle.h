@@ -36,6 +36,8 @@ typedef struct orc_params {
     double X0[3], U0[3], W0[3];
     int32_t noise_diffusive;   /* 1: antisymmetric species-momentum noise              */
     int32_t fixed_velocity;    /* 1: sphere keeps U0, W0 (prescribed motion)          */
+    int32_t init_split;        /* > 0: planes z >= init_split start from the swapped  */
+                               /* densities (rho0[1], rho0[0]), the other phase       */
 } orc_params;
 
 typedef struct orc_particle {

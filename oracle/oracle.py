@@ -24,6 +24,7 @@ class OrcParams(C.Structure):
         ("radius", C.c_double), ("rho_p", C.c_double), ("wet_drho", C.c_double),
         ("X0", C.c_double * 3), ("U0", C.c_double * 3), ("W0", C.c_double * 3),
         ("noise_diffusive", C.c_int32), ("fixed_velocity", C.c_int32),
+        ("init_split", C.c_int32),
     ]
 
 
@@ -75,7 +76,7 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.
                 tau_shear=1.0, tau_bulk=1.0, tau_mom=1.0, tau_ghost=1.0, kT=0.0, seed=0,
                 replica=0, g=(0.0, 0.0, 0.0), force_mode=0, radius=0.0, rho_p=2.0,
                 wet_drho=0.0, X0=None, U0=(0.0, 0.0, 0.0), W0=(0.0, 0.0, 0.0),
-                noise_diffusive=1, fixed_velocity=0)
+                noise_diffusive=1, fixed_velocity=0, init_split=0)
 
 
 def make_params(d: dict) -> OrcParams:

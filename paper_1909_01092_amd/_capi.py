@@ -24,7 +24,7 @@ class LbmParams(C.Structure):
         ("radius", C.c_double), ("rho_p", C.c_double), ("wet_drho", C.c_double),
         ("X0", C.c_double * 3), ("U0", C.c_double * 3), ("W0", C.c_double * 3),
         ("noise_diffusive", C.c_int32), ("fixed_velocity", C.c_int32),
-        ("series_cap", C.c_int32), ("reserved", C.c_int32),
+        ("series_cap", C.c_int32), ("init_split", C.c_int32),
     ]
 
 

@@ -119,6 +119,8 @@ std::string validate(const lbm_params *p, int n, int prec) {
         if (!(q.rho0[0] > 0.0) || !(q.rho0[1] > 0.0)) return fmt("replica %d: rho0 must be > 0", r);
         if (!(q.init_amp >= 0.0) || q.init_amp >= std::min(q.rho0[0], q.rho0[1]))
             return fmt("replica %d: init_amp must be in [0, min(rho0))", r);
+        if (q.init_split < 0 || q.init_split >= q.nz)
+            return fmt("replica %d: init_split must be in [0, nz)", r);
         const double taus[4] = {q.tau_shear, q.tau_bulk, q.tau_mom, q.tau_ghost};
         for (double t : taus)
             if (!(t > 0.5) || !std::isfinite(t)) return fmt("replica %d: relaxation times must be > 1/2", r);
@@ -521,6 +523,7 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
             if (t != 1.0) c->tau1 = 0;
         D.kT = q.kT;
         D.init_amp = q.init_amp;
+        D.init_split = q.init_split;
         D.key0 = (uint32_t)(q.seed & 0xffffffffu);
         D.key1 = (uint32_t)(q.seed >> 32) ^ (uint32_t)q.replica;
         D.noise_diffusive = q.noise_diffusive;

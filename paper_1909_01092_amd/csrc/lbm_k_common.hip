@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void k_init_layer(InitArgs a) {
         uint32_t c0 = (uint32_t)nidx(x, y, z, g), c1 = 0u, c2 = 0u, c3 = 1u;
         philox4x32_10(c0, c1, c2, c3, D.key0, D.key1);
         const uint32_t w = l == 0 ? c0 : c1;
-        return D.rho0[l] + D.init_amp * (2.0 * (((double)w + 0.5) * 0x1p-32) - 1.0);
+        const bool swap = D.init_split > 0 && z >= D.init_split;  // other phase above the split
+        return (swap ? D.rho0[1 - l] : D.rho0[l]) + D.init_amp * (2.0 * (((double)w + 0.5) * 0x1p-32) - 1.0);
     };
     double ns[1] = {0.0};
     for (int b = threadIdx.x; b < S3; b += 256) {

@@ -1065,7 +1065,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
 
 // ================================================================ k_init
 // f(0) = w_i rho_l(x) with rho_l = rho0_l + amp (2u - 1), u from Philox with
-// counter (node, 0, 0, 1), word l, written into the slots x pulls from.
+// counter (node, 0, 0, 1), word l, written into the slots x pulls from; the
+// planes z >= init_split (when set) start from the swapped pair rho0_{1-l}.
 template <typename S>
 __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     __shared__ double red[4 * 2];
@@ -1085,8 +1086,10 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
         const uint32_t w[2] = {c0, c1};
         S *dst = reinterpret_cast<S *>(a.buf) + D.pop_off;
         const uint32_t own = pidx(x, y, z, g);
+        const bool swap = D.init_split > 0 && z >= D.init_split;  // other phase above the split
         for (int l = 0; l < 2; l++) {
-            const double rho = D.rho0[l] + D.init_amp * (2.0 * (((double)w[l] + 0.5) * 0x1p-32) - 1.0);
+            const double base = swap ? D.rho0[1 - l] : D.rho0[l];
+            const double rho = base + D.init_amp * (2.0 * (((double)w[l] + 0.5) * 0x1p-32) - 1.0);
             if (solid) continue;
             m[l] = rho;
             for (int i = 0; i < Q; i++) {

@@ -44,6 +44,8 @@ struct RepDesc {
     double init_amp;
     uint32_t key0, key1;
     int32_t noise_diffusive, fixed_velocity;
+    int32_t init_split;      // first plane of the swapped initial phase (0: none)
+    int32_t pad_split;
 };
 
 struct RepState {

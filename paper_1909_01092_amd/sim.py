@@ -15,8 +15,6 @@ from .workloads import full
 
 def _fill(p: _capi.LbmParams, q: dict):
     for name, ctype in _capi.LbmParams._fields_:
-        if name == "reserved":
-            continue
         v = q[name]
         if hasattr(ctype, "_length_"):
             setattr(p, name, ctype(*[float(x) for x in v]))

@@ -10,7 +10,7 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.
                 tau_shear=1.0, tau_bulk=1.0, tau_mom=1.0, tau_ghost=1.0, kT=0.0, seed=0,
                 replica=0, g=(0.0, 0.0, 0.0), force_mode=0, radius=0.0, rho_p=2.0,
                 wet_drho=0.0, X0=None, U0=(0.0, 0.0, 0.0), W0=(0.0, 0.0, 0.0),
-                noise_diffusive=1, fixed_velocity=0, series_cap=4096)
+                noise_diffusive=1, fixed_velocity=0, series_cap=4096, init_split=0)
 
 
 def full(params: dict) -> dict:
@@ -90,3 +90,21 @@ def paper_box(n: int = 60, nz: int = 900, radius: float = 8.0, kT: float = 1e-4,
                      rho_p=2.0 * rho_tot, kT=kT, radius=radius, g=(0.0, 0.0, g), seed=9,
                      X0=((n - 1) / 2.0, (n - 1) / 2.0, min(nz / 4.0, 3.0 * radius + 4.0)),
                      series_cap=steps_cap))
+
+
+# contact angle of the wetting layer: the sphere centred on a flat interface
+# between the two demixed phases of PAPER_RHO0 (A below the plane
+# z = n/2 - 1/2, B above) in a closed n^3 box with neutral walls, no noise, no
+# driving, one replica per wetting offset Delta rho
+WETTING_N = 48
+WETTING_R = 8.0
+WETTING_DRHO = (-0.2, -0.15, -0.1, -0.05, 0.0, 0.05, 0.1, 0.15, 0.2)
+
+
+def wetting(drhos=WETTING_DRHO, n: int = WETTING_N, radius: float = WETTING_R,
+            steps_cap: int = 16384) -> list:
+    rho_tot = PAPER_RHO0[0] + PAPER_RHO0[1]
+    return [full(dict(nx=n, ny=n, nz=n, walls=7, rho0=PAPER_RHO0, init_amp=0.0, G=1.5,
+                      init_split=n // 2, rho_p=2.0 * rho_tot, kT=0.0, radius=radius, wet_drho=d,
+                      seed=0, replica=k, series_cap=steps_cap))
+            for k, d in enumerate(drhos)]

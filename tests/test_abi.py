@@ -66,6 +66,7 @@ def test_workspace_sizes(capi):
     dict(nx=16, ny=16, nz=16, walls=3, radius=7.5),           # sphere touches a wall
     dict(nx=12, ny=12, nz=12, radius=3.5),                    # periodic box too short for the bbox
     dict(nx=16, ny=16, nz=32, walls=3, radius=3.0, U0=(0.0, 0.0, 0.6)),
+    dict(init_split=-1), dict(init_split=16),                 # split plane outside the lattice
 ])
 def test_invalid_parameters_rejected(capi, bad):
     from paper_1909_01092_amd.sim import workspace_bytes

@@ -17,6 +17,10 @@ never against a re-typed copy of the oracle's own formula:
   * invariants: per-component mass with a moving sphere and cover/uncover
     events, total momentum of fluid + particle, zero force on a co-moving
     sphere;
+  * the A <-> B mirror symmetry of a sphere at a flat interface between the
+    two demixed phases: Delta rho = 0 keeps it on the interface, +-Delta rho
+    give mirror-image motions, and Delta rho > 0 (affinity to A) draws it
+    into the A phase;
   * brute force: an independent dense-matrix, population-space restatement
     of the whole step (tests/brute_force.py) on a tiny walled channel with a
     moving sphere, which planted mistakes in the oracle fail;
@@ -431,6 +435,36 @@ def test_co_moving_sphere_feels_no_force(oracle_lib):
         assert np.abs(p["T"]).max() < 1e-13
         np.testing.assert_allclose(p["U"], U, rtol=1e-12)
     assert p["n_covered"] == 0 and p["n_uncovered"] == 0
+
+
+_IFACE = dict(nx=10, ny=10, nz=16, walls=7, rho0=(2.21, 0.09), G=1.5, init_split=8, radius=2.5,
+              rho_p=4.6)
+
+
+def test_sphere_at_interface_mirror_symmetry(oracle_lib):
+    """Closed box, A phase below z = 7.5 and B phase above (the paper's
+    demixed densities), sphere centred on the interface, no noise, no
+    driving.  Mirroring z about the interface and exchanging A and B maps the
+    problem onto itself with Delta rho -> -Delta rho (the wetting layer adds
+    +Delta rho to A and -Delta rho to B, Sec. 2 particle paragraph), so:
+    Delta rho = 0 leaves the sphere on the interface, +-Delta rho move it by
+    mirror-image displacements, and it stays on the box axis.  A positive
+    offset (affinity to A) draws it into the A phase."""
+    z0 = (_IFACE["nz"] - 1) / 2.0
+    runs = {}
+    for d in (0.0, 0.3, -0.3):
+        s = oracle_lib.OracleSim(dict(_IFACE, wet_drho=d))
+        s.step(100)
+        runs[d] = s.particle()
+    p0 = runs[0.0]
+    assert abs(p0["X"][2] - z0) < 1e-13 and np.abs(p0["U"]).max() < 1e-14
+    up, dn = runs[0.3], runs[-0.3]
+    assert abs((up["X"][2] - z0) + (dn["X"][2] - z0)) < 1e-12
+    assert abs(up["U"][2] + dn["U"][2]) < 1e-13
+    for p in (up, dn):
+        np.testing.assert_allclose(p["X"][:2], [4.5, 4.5], atol=1e-12)
+    assert up["X"][2] < z0 - 0.5, up["X"]
+    assert up["n_covered"] > 0 and up["n_uncovered"] > 0
 
 
 # ---------------------------------------------------------------- adjoint
