@@ -45,6 +45,7 @@ struct ParticleArgs {
     const double *raw;
     double *vrho;              // wetting-layer densities of step n+1, written
     double *series;
+    int32_t finish_apart;      // 1: k_finish publishes the step; 0: the last workgroup does
 };
 
 struct InitArgs {

@@ -636,15 +636,28 @@ __device__ __forceinline__ T store_round(double v, T inv_scale, T scale, S &sv) 
 }
 
 // Mean post-streaming density of the neighbours of p that are fluid at X^n
-// and at X^{n+1} (raw of the box at orgo); rho0 when there is none.
-__device__ __noinline__ void mean_kept(const int (&p)[3], const double *Xo, const double *Xn, double R2,
-                                          const double *raw, const int32_t *orgo, int Sx, int S3,
-                                          const Geo &g, const double *rho0, double (&rb)[2]) {
+// and at X^{n+1} (raw of the box at orgo); rho0 when there is none.  Out of
+// line (it runs only next to uncovered nodes), with every argument passed by
+// value so that the caller keeps nothing in scratch memory for the call.
+struct Rho2 {
+    double a, b;
+};
+struct Pos3 {
+    double v[3];
+};
+struct Org3 {
+    int32_t v[3];
+};
+
+__device__ __noinline__ Rho2 mean_kept(int px, int py, int pz, Pos3 Xo, Pos3 Xn, double R2,
+                                        const double *raw, Org3 orgo, int Sx, int S3, Geo g,
+                                        double rho0A, double rho0B) {
+    const int p[3] = {px, py, pz};
     Nbr no, nn;
-    nbr_of(p, Xo, g, no);
-    nbr_of(p, Xn, g, nn);
+    nbr_of(p, Xo.v, g, no);
+    nbr_of(p, Xn.v, g, nn);
     int bo[3];
-    const bool inbox = box_coords(p, orgo, Sx, g, bo);
+    const bool inbox = box_coords(p, orgo.v, Sx, g, bo);
     int idx[Q];
     uint32_t keep = 0;
 #pragma unroll
@@ -661,8 +674,10 @@ __device__ __noinline__ void mean_kept(const int (&p)[3], const double *Xo, cons
         s1 += raw[S3 + idx[i]];
     }
     const int cnt = __builtin_popcount(keep);
-    rb[0] = cnt > 0 ? s0 / cnt : rho0[0];
-    rb[1] = cnt > 0 ? s1 / cnt : rho0[1];
+    Rho2 rb;
+    rb.a = cnt > 0 ? s0 / cnt : rho0A;
+    rb.b = cnt > 0 ? s1 / cnt : rho0B;
+    return rb;
 }
 
 // =============================================================== k_links
@@ -842,9 +857,89 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
 //  * particle node at X^{n+1}: gets the wetting-layer density, mean of its
 //    fluid neighbours +/- Delta rho (the mass correction delta is added
 //    where it is read).
-// The last workgroup sums the event partials, computes the global mass
-// correction and publishes the state of step n+1.
-template <typename S, typename T, int B>
+// Each workgroup leaves its event sums as a partial.  They are combined, with
+// the global mass correction and the new state of step n+1, either by the
+// last workgroup to finish (one device-scope fence and atomic per workgroup)
+// or, for large grids, by the separate k_finish launch (finish_apart): each
+// such fence writes back the XCD's L2, which costs more than a launch once
+// many workgroups share an XCD.
+// Leap-frog Newton-Euler step of one sphere from the link sums of step n
+// (momentum exchange minus wetting-layer reaction, plus F_ext and the
+// pending event momentum), and the bounding-box origin of X^{n+1}.  Every
+// caller evaluates it on the same inputs, so all agree bitwise.
+struct Motion {
+    double F[3], Tq[3], Un[3], Wn[3], Xn[3];
+    int org[3];
+};
+
+__device__ __forceinline__ void newton_euler(const RepDesc &D, const RepState *st, const Geo &g,
+                                             const double (&sum)[15], Motion &m) {
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    const bool w3[3] = {g.wx, g.wy, g.wz};
+    for (int q = 0; q < 3; q++) {
+        m.F[q] = sum[q] - sum[8 + q] + D.Fext[q] + st->Pev[q];
+        m.Tq[q] = sum[3 + q] - sum[11 + q] + st->Lev[q];
+        m.Un[q] = D.fixed_velocity ? st->U[q] : st->U[q] + m.F[q] / D.mp;
+        m.Wn[q] = D.fixed_velocity ? st->W[q] : st->W[q] + m.Tq[q] / D.Ip;
+    }
+    for (int q = 0; q < 3; q++) {
+        m.Xn[q] = st->X[q] + m.Un[q];
+        if (!w3[q]) {
+            if (m.Xn[q] >= n3[q]) m.Xn[q] -= n3[q];
+            else if (m.Xn[q] < 0.0) m.Xn[q] += n3[q];
+        }
+        m.org[q] = (int)floor(m.Xn[q] - D.radius) - 2;  // box of X^{n+1}
+    }
+}
+
+// A replica without a sphere: record U = 0 and advance the step counter.
+__device__ __forceinline__ void advance_empty(const ParticleArgs &a, const RepDesc &D, RepState *st) {
+    const int64_t n = st->step;
+    double *s = a.series + D.series_off + 3 * (n % D.series_cap);
+    s[0] = s[1] = s[2] = 0.0;
+    st->delta[0] = st->delta[1] = 0.0;
+    st->step = n + 1;
+}
+
+// Publish step n+1 of one replica from the link sums, the motion and the
+// event totals (one thread): global mass correction
+// delta_l = -(bounce-back flux - covered + uncovered mass)_l / |Phi^{n+1}|,
+// pending event momentum, the U series entry and the stability flags.
+__device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDesc &D, RepState *st,
+                                             const Geo &g, const double (&sum)[15], const Motion &mo,
+                                             const double (&tot)[20]) {
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    const bool w3[3] = {g.wx, g.wy, g.wz};
+    const double Xold[3] = {st->X[0], st->X[1], st->X[2]};
+    const double *utot = tot + 10;
+    const double nf = (double)D.N - tot[9];
+    const int64_t n = st->step;
+    double *s = a.series + D.series_off + 3 * (n % D.series_cap);
+    bool bad = false;
+    for (int l = 0; l < 2; l++) st->delta[l] = -(sum[6 + l] - tot[6 + l] + utot[6 + l]) / nf;
+    for (int q = 0; q < 3; q++) {
+        st->Xp[q] = Xold[q];
+        st->X[q] = mo.Xn[q];
+        st->U[q] = mo.Un[q];
+        st->W[q] = mo.Wn[q];
+        st->F[q] = mo.F[q];
+        st->T[q] = mo.Tq[q];
+        st->Pev[q] = tot[q] - utot[q];
+        st->Lev[q] = tot[3 + q] - utot[3 + q];
+        st->org[q] = mo.org[q];
+        s[q] = mo.Un[q];
+        if (!(fabs(mo.Un[q]) < 0.5) || !isfinite(mo.F[q])) bad = true;
+        if (w3[q] && (mo.Xn[q] - D.radius < -0.5 || mo.Xn[q] + D.radius > n3[q] - 0.5)) bad = true;
+    }
+    st->n_fluid = nf;
+    st->n_cov += (int64_t)tot[8];
+    st->n_unc += (int64_t)utot[8];
+    st->n_links = (int64_t)sum[14];
+    if (bad) st->flags |= FLAG_UNSTABLE;
+    st->step = n + 1;
+}
+
+template <typename S, typename T, int B, bool APART>
 __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     __shared__ double red[(B / 64) * 20];
     __shared__ int last;
@@ -855,45 +950,25 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     const Geo g = geo_of(D);
     const int t = threadIdx.x;
     const int local = wg - D.k3_begin;
-    double *series = a.series + D.series_off;
-
     if (!D.has_particle) {
-        if (t == 0) {
-            const int64_t n = st->step;
-            double *s = series + 3 * (n % D.series_cap);
-            s[0] = s[1] = s[2] = 0.0;
-            st->delta[0] = st->delta[1] = 0.0;
-            st->step = n + 1;
-        }
+        if (!APART && t == 0) advance_empty(a, D, st);
         return;
     }
-    double X[3], U[3], Wv[3];
+    double X[3];
     int32_t orgo[3];
     for (int q = 0; q < 3; q++) {
-        X[q] = st->X[q]; U[q] = st->U[q]; Wv[q] = st->W[q]; orgo[q] = st->org[q];
+        X[q] = st->X[q]; orgo[q] = st->org[q];
     }
     // 1. link momentum exchange and wetting-layer reaction of step n
     double sum[15];
     sum_partials<15>(a.part1 + D.part3_off, D.k3_count, 0, sum);
     // 2. Newton-Euler, leap-frog
-    double F[3], Tq[3], Un[3], Wn[3], Xn[3];
-    const int n3[3] = {g.nx, g.ny, g.nz};
-    const bool w3[3] = {g.wx, g.wy, g.wz};
-    for (int q = 0; q < 3; q++) {
-        F[q] = sum[q] - sum[8 + q] + D.Fext[q] + st->Pev[q];
-        Tq[q] = sum[3 + q] - sum[11 + q] + st->Lev[q];
-        Un[q] = D.fixed_velocity ? U[q] : U[q] + F[q] / D.mp;
-        Wn[q] = D.fixed_velocity ? Wv[q] : Wv[q] + Tq[q] / D.Ip;
-    }
-    int org[3];
-    for (int q = 0; q < 3; q++) {
-        Xn[q] = X[q] + Un[q];
-        if (!w3[q]) {
-            if (Xn[q] >= n3[q]) Xn[q] -= n3[q];
-            else if (Xn[q] < 0.0) Xn[q] += n3[q];
-        }
-        org[q] = (int)floor(Xn[q] - D.radius) - 2;  // box of X^{n+1}
-    }
+    Motion mo;
+    newton_euler(D, st, g, sum, mo);
+    const double(&Un)[3] = mo.Un;
+    const double(&Wn)[3] = mo.Wn;
+    const double(&Xn)[3] = mo.Xn;
+    const int(&org)[3] = mo.org;
     const int Sx = D.S, S3 = Sx * Sx * Sx;
     const double *raw = a.raw + D.bbox_off * RAW;
     double *vrho = a.vrho + D.bbox_off * 2;
@@ -948,11 +1023,12 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
             const int i = __builtin_ctz(m);
             int q[3];
             nb_pos(p, i, g, q);
-            double rb[2];
-            mean_kept(q, X, Xn, D.R2, raw, orgo, Sx, S3, g, D.rho0, rb);
+            const Rho2 rb = mean_kept(q[0], q[1], q[2], Pos3{{X[0], X[1], X[2]}}, Pos3{{Xn[0], Xn[1], Xn[2]}},
+                                      D.R2, raw, Org3{{orgo[0], orgo[1], orgo[2]}}, Sx, S3, g,
+                                      D.rho0[0], D.rho0[1]);
 #pragma unroll
             for (int k = 1; k < Q; k++)
-                if (k == i) { r0[k] = rb[0]; r1[k] = rb[1]; }
+                if (k == i) { r0[k] = rb.a; r1[k] = rb.b; }
         }
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -987,8 +1063,10 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
         }
     }
     if (in && !fo && fn) {  // uncovered (rare): its loads, then its stores
-        double rb[2];
-        mean_kept(p, X, Xn, D.R2, raw, orgo, Sx, S3, g, D.rho0, rb);
+        const Rho2 rbk = mean_kept(p[0], p[1], p[2], Pos3{{X[0], X[1], X[2]}}, Pos3{{Xn[0], Xn[1], Xn[2]}},
+                                   D.R2, raw, Org3{{orgo[0], orgo[1], orgo[2]}}, Sx, S3, g,
+                                   D.rho0[0], D.rho0[1]);
+        const double rb[2] = {rbk.a, rbk.b};
         const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
                               sepd(p[2] - Xn[2], g.nz, g.wz)};
         const double u[3] = {Un[0] + Wn[1] * rr[2] - Wn[2] * rr[1],
@@ -1022,45 +1100,42 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
         double *pp = a.part3 + D.part3_off + (int64_t)local * PART;
         for (int k = 0; k < 20; k++) pp[k] = ev[k];
     }
+    if constexpr (APART) return;
     __threadfence();
     __syncthreads();
     if (t == 0) last = (atomicAdd(&st->k3_done, 1u) == (unsigned)(D.k3_count - 1));
     __syncthreads();
     if (!last) return;
     __threadfence();
-
-    // ---- last workgroup: event sums (fixed order), mass correction, new state
+    // last workgroup: event sums (fixed order), then the new state
     double tot[20];
     sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
     if (t != 0) return;
-    const double *utot = tot + 10;
-    const double nf = (double)D.N - tot[9];
-    const int64_t n = st->step;
-    double *s = series + 3 * (n % D.series_cap);
-    bool bad = false;
-    for (int l = 0; l < 2; l++) st->delta[l] = -(sum[6 + l] - tot[6 + l] + utot[6 + l]) / nf;
-    for (int q = 0; q < 3; q++) {
-        st->Xp[q] = X[q];
-        st->X[q] = Xn[q];
-        st->U[q] = Un[q];
-        st->W[q] = Wn[q];
-        st->F[q] = F[q];
-        st->T[q] = Tq[q];
-        st->Pev[q] = tot[q] - utot[q];
-        st->Lev[q] = tot[3 + q] - utot[3 + q];
-        st->org[q] = org[q];
-        s[q] = Un[q];
-        if (!(fabs(Un[q]) < 0.5) || !isfinite(F[q])) bad = true;
-        if (w3[q] && (Xn[q] - D.radius < -0.5 || Xn[q] + D.radius > n3[q] - 0.5)) bad = true;
-    }
-    st->n_fluid = nf;
-    st->n_cov += (int64_t)tot[8];
-    st->n_unc += (int64_t)utot[8];
-    st->n_links = (int64_t)sum[14];
-    if (bad) st->flags |= FLAG_UNSTABLE;
     st->k3_done = 0;
-    st->step = n + 1;
+    publish_step(a, D, st, g, sum, mo, tot);
     __threadfence();
+}
+
+// ============================================================== k_finish
+// One wave per replica after k_particle (finish_apart): sums the link and
+// event partials in the same fixed order, repeats the Newton-Euler step of
+// k_particle on the same inputs and publishes the state of step n+1.
+template <int B>
+__global__ __launch_bounds__(B) void k_finish(ParticleArgs a) {
+    const int r = blockIdx.x;
+    const RepDesc D = a.desc[r];
+    RepState *st = a.state + r;
+    if (!D.has_particle) {
+        if (threadIdx.x == 0) advance_empty(a, D, st);
+        return;
+    }
+    const Geo g = geo_of(D);
+    double sum[15], tot[20];
+    sum_partials<15>(a.part1 + D.part3_off, D.k3_count, 0, sum);
+    sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
+    Motion mo;
+    newton_euler(D, st, g, sum, mo);
+    if (threadIdx.x == 0) publish_step(a, D, st, g, sum, mo, tot);
 }
 
 // ================================================================ k_init
@@ -1204,7 +1279,11 @@ hipError_t launch_links_t(const LinkArgs &a, int grid, hipStream_t s) {
 
 template <typename S, typename T>
 hipError_t launch_particle_t(const ParticleArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_particle<S, T, 256>), dim3(grid), dim3(256), 0, s, a);
+    if (a.finish_apart) hipLaunchKernelGGL((k_particle<S, T, 256, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_particle<S, T, 256, false>), dim3(grid), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.finish_apart) return e;
+    hipLaunchKernelGGL(k_finish<64>, dim3(a.nrep), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ struct RepState {
     int32_t org[3];          // origin of the bounding box of X^n
     int32_t pad_org;
     uint32_t flags;          // bit0 unstable
-    uint32_t k3_done;        // particle-kernel completion counter
+    uint32_t k3_done;        // particle-kernel completion counter (0 between steps)
     uint32_t pad1[2];
 };
 

@@ -208,6 +208,30 @@ def test_ensemble_of_uneven_replicas(Sim):
         compare(sim, r, 1e-12, rep=k, what=f"ensemble replica {k}")
 
 
+def test_many_replicas_finish_apart_fp64(Sim):
+    """Forty replicas, enough particle workgroups (273) that the step is
+    finished by its own launch rather than by the last workgroup: every
+    sphere moves fast enough for cover / uncover events, one replica has no
+    sphere; three of them against the oracle."""
+    reps = []
+    for k in range(40):
+        if k == 20:
+            reps.append(workloads.full(dict(nx=12, ny=12, nz=16, walls=3, kT=1e-5, init_amp=1e-3,
+                                            G=1.5, seed=11, replica=k)))
+            continue
+        reps.append(workloads.channel(12, 16, kT=1e-5, radius=2.5, g=(0, 0, 5e-5), seed=11, replica=k,
+                                      U0=(0.0, 0.01 * (k % 3), 0.1), wet_drho=0.05 * (k % 4)))
+    sim = Sim(reps, "fp64")
+    sim.step(25)
+    for k in (0, 20, 39):
+        ref = OracleSim(reps[k])
+        ref.step(25)
+        compare(sim, ref, 1e-12, rep=k, what=f"replica {k} of 40")
+        if k != 20:
+            pg, po = compare_particle(sim, ref, 1e-10, rep=k, what=f"replica {k} of 40")
+            assert po["n_covered"] > 0 and po["n_uncovered"] > 0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_launch_shape_does_not_change_results(Sim, prec):
     """Block sizes 256 / 512 / 1024 and z-chunks with ragged tails and both
