@@ -25,7 +25,7 @@ thread_local std::string g_init_error;
 constexpr size_t ALIGN = 256;
 constexpr int MAIN_BLOCK_MIN = 256;
 constexpr size_t MAIN_LDS_MAX = 64 * 1024;
-constexpr int K3_BLOCK = 256;
+constexpr int K3_BLOCK = K3_THREADS;
 constexpr int K3_FINISH_APART = 256;  // particle workgroups above which k_finish runs apart
 constexpr int INIT_BLOCK = 256;
 
@@ -344,7 +344,7 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     // many particle workgroups: a separate finishing launch beats one
     // device-scope fence per workgroup (192-replica ensemble: 4.02 against
     // 4.30 ms per step); few: the fences are cheaper than the extra launch
-    // (single channel, 42 workgroups: 0.141 against 0.144 ms per step)
+    // (64x64x256 channel, 168 workgroups: 0.1365 against 0.1403 ms per step)
     pa.finish_apart = c->k3_grid > K3_FINISH_APART ? 1 : 0;
     e = launch_particle(c->prec, pa, c->k3_grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "particle kernel launch");

@@ -1273,14 +1273,14 @@ hipError_t launch_main_t(const MainArgs &a, int grid, int block, size_t lds, hip
 
 template <typename S, typename T>
 hipError_t launch_links_t(const LinkArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_links<S, T, 256>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_links<S, T, K3_THREADS>), dim3(grid), dim3(K3_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename S, typename T>
 hipError_t launch_particle_t(const ParticleArgs &a, int grid, hipStream_t s) {
-    if (a.finish_apart) hipLaunchKernelGGL((k_particle<S, T, 256, true>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_particle<S, T, 256, false>), dim3(grid), dim3(256), 0, s, a);
+    if (a.finish_apart) hipLaunchKernelGGL((k_particle<S, T, K3_THREADS, true>), dim3(grid), dim3(K3_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_particle<S, T, K3_THREADS, false>), dim3(grid), dim3(K3_THREADS), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.finish_apart) return e;
     hipLaunchKernelGGL(k_finish<64>, dim3(a.nrep), dim3(64), 0, s, a);
