@@ -941,8 +941,12 @@ __device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDes
 
 template <typename S, typename T, int B, bool APART>
 __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
+    static_assert(B == 64, "the uncovered-density jobs are shared within one wave");
     __shared__ double red[(B / 64) * 20];
     __shared__ int last;
+    __shared__ int job_desc[64];   // owner lane | direction << 8 (0: the owner itself)
+    __shared__ int job_pos[64][3];
+    __shared__ Rho2 job_res[64];
     const int wg = blockIdx.x;
     const int r = find_rep(a.k3_begin, a.nrep, wg);
     const RepDesc D = a.desc[r];  // by value: no reload after stores
@@ -981,7 +985,7 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
 #pragma unroll
     for (int k = 0; k < 20; k++) ev[k] = 0.0;
     const int b = local * B + t;
-    int bb[3], p[3];
+    int bb[3] = {0, 0, 0}, p[3] = {0, 0, 0};
     const bool in = b < S3 && bbox_pos(b, org, Sx, g, bb, p);
     Nbr no, nn;
     nbr_of(p, X, g, no);
@@ -992,11 +996,19 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     const bool inbox = box_coords(p, orgo, Sx, g, bo);
     // Loads and arithmetic first, every store last (loads and stores share
     // one wait counter here).
-    double vw[2] = {0.0, 0.0};
-    if (in && !fn) {  // particle node at X^{n+1} (covered ones included): wetting layer
-        ev[9] += 1.0;
-        int idx[Q];
-        uint32_t kept = 0, fresh = 0;  // fluid at X^{n+1}; of those, uncovered now
+    //
+    // A particle node at X^{n+1} (covered ones included) takes the wetting
+    // layer: the mean density of its neighbours fluid at X^{n+1}.  A neighbour
+    // uncovered at this step carries the mean density of its own kept
+    // neighbours (its f_eq density), and an uncovered node needs that mean for
+    // itself.  Those means are jobs shared out over the wave's lanes, 64 per
+    // round, so that a lane with several of them does not run them one after
+    // another while the rest of the wave waits.
+    const bool pn = in && !fn;         // particle node at X^{n+1}
+    const bool unc = in && !fo && fn;  // uncovered at this step
+    int idx[Q];
+    uint32_t kept = 0, fresh = 0;  // fluid at X^{n+1}; of those, uncovered now
+    if (pn) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             idx[i] = -1;
@@ -1009,6 +1021,56 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
             }
             kept |= 1u << i;
         }
+    }
+    const uint32_t jobs = pn ? fresh : (unc ? 1u : 0u);  // bit i: neighbour i; bit 0: itself
+    double fs[2] = {0.0, 0.0};  // fresh neighbours' densities, summed in direction order
+    Rho2 rself = {0.0, 0.0};    // an uncovered node's own mean
+    {
+        const int cnt = __builtin_popcount(jobs);
+        int incl = cnt;  // inclusive prefix sum of the job counts over the wave
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (t >= d) incl += v;
+        }
+        const int excl = incl - cnt;
+        const int total = __shfl(incl, 63);
+        if (total > 0) {  // uniform over the wave (one wave per workgroup)
+            job_pos[t][0] = p[0];
+            job_pos[t][1] = p[1];
+            job_pos[t][2] = p[2];
+            for (int base = 0; base < total; base += 64) {
+                int m = excl;
+                for (uint32_t w = jobs; w; w &= w - 1, m++)
+                    if (m >= base && m < base + 64) job_desc[m - base] = t | (__builtin_ctz(w) << 8);
+                __syncthreads();
+                if (t < total - base) {
+                    const int d = job_desc[t], owner = d & 255, i = d >> 8;
+                    const int o[3] = {job_pos[owner][0], job_pos[owner][1], job_pos[owner][2]};
+                    int q[3] = {o[0], o[1], o[2]};
+                    if (i > 0) nb_pos(o, i, g, q);
+                    job_res[t] = mean_kept(q[0], q[1], q[2], Pos3{{X[0], X[1], X[2]}}, Pos3{{Xn[0], Xn[1], Xn[2]}},
+                                           D.R2, raw, Org3{{orgo[0], orgo[1], orgo[2]}}, Sx, S3, g,
+                                           D.rho0[0], D.rho0[1]);
+                }
+                __syncthreads();
+                m = excl;
+                for (uint32_t w = jobs; w; w &= w - 1, m++) {
+                    if (m < base || m >= base + 64) continue;
+                    const Rho2 rb = job_res[m - base];
+                    if (__builtin_ctz(w) == 0) {
+                        rself = rb;
+                    } else {
+                        fs[0] += rb.a;
+                        fs[1] += rb.b;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    double vw[2] = {0.0, 0.0};
+    if (pn) {
+        ev[9] += 1.0;
         double r0[Q], r1[Q];
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -1018,25 +1080,15 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
                 r1[i] = raw[S3 + idx[i]];
             }
         }
-        // a neighbour uncovered at this step carries its f_eq density (rare)
-        for (uint32_t m = fresh; m; m &= m - 1) {
-            const int i = __builtin_ctz(m);
-            int q[3];
-            nb_pos(p, i, g, q);
-            const Rho2 rb = mean_kept(q[0], q[1], q[2], Pos3{{X[0], X[1], X[2]}}, Pos3{{Xn[0], Xn[1], Xn[2]}},
-                                      D.R2, raw, Org3{{orgo[0], orgo[1], orgo[2]}}, Sx, S3, g,
-                                      D.rho0[0], D.rho0[1]);
-#pragma unroll
-            for (int k = 1; k < Q; k++)
-                if (k == i) { r0[k] = rb.a; r1[k] = rb.b; }
-        }
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            if (!((kept >> i) & 1u)) continue;
+            if (!(((kept & ~fresh) >> i) & 1u)) continue;
             s0 += r0[i];
             s1 += r1[i];
         }
+        s0 += fs[0];
+        s1 += fs[1];
         const int cnt = __builtin_popcount(kept);
         vw[0] = cnt > 0 ? s0 / cnt + D.drho : 0.0;
         vw[1] = cnt > 0 ? s1 / cnt - D.drho : 0.0;
@@ -1062,11 +1114,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
             vrho[S3 + b] = vw[1];
         }
     }
-    if (in && !fo && fn) {  // uncovered (rare): its loads, then its stores
-        const Rho2 rbk = mean_kept(p[0], p[1], p[2], Pos3{{X[0], X[1], X[2]}}, Pos3{{Xn[0], Xn[1], Xn[2]}},
-                                   D.R2, raw, Org3{{orgo[0], orgo[1], orgo[2]}}, Sx, S3, g,
-                                   D.rho0[0], D.rho0[1]);
-        const double rb[2] = {rbk.a, rbk.b};
+    if (unc) {  // uncovered (rare): f_eq of its neighbours' mean density and u_b
+        const double rb[2] = {rself.a, rself.b};
         const double rr[3] = {sepd(p[0] - Xn[0], g.nx, g.wx), sepd(p[1] - Xn[1], g.ny, g.wy),
                               sepd(p[2] - Xn[2], g.nz, g.wz)};
         const double u[3] = {Un[0] + Wn[1] * rr[2] - Wn[2] * rr[1],
