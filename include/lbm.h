@@ -191,11 +191,14 @@ int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph);
  * Results are identical either way.  Synchronises the context stream. */
 int lbm_set_overlap(lbm_ctx *c, int32_t enable);
 
-/* Timing of the main kernel: while enabled, every plain-launch step records
- * HIP events around the main-kernel launch (its far-tile part when steps are
- * overlapped) on the stream it runs on.  lbm_timing_read returns the mean
- * duration (ms) and the number of timed launches since it was enabled. */
-int lbm_timing(lbm_ctx *c, int32_t enable);
+/* Timing of the main kernel.  every = 0 turns it off; every = k >= 1 makes
+ * every k-th plain-launch step from now on (the first, the (k+1)-th, ...)
+ * record HIP events around its main-kernel launch (its far-tile part when
+ * steps are overlapped) on the stream it runs on.  A sparse sample keeps
+ * the events' own cost out of the other steps.  lbm_timing_read returns the
+ * mean duration (ms) and the number of timed launches since it was enabled.
+ * EINVAL for every < 0. */
+int lbm_timing(lbm_ctx *c, int32_t every);
 int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count);
 
 /* Algorithmic bytes the timed main-kernel launch moves per step (read +

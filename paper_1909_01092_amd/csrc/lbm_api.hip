@@ -177,6 +177,8 @@ struct lbm_ctx {
     int graph_steps = 0, graph_parity = -1;
     hipGraphExec_t gexec = nullptr;
     bool timing = false;
+    int timing_every = 1;     // plain-launch steps: events around every k-th main launch
+    int64_t timing_step = 0;  // plain-launch steps since timing was enabled
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
     std::string err;
@@ -623,7 +625,8 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
         }
     }
     for (int32_t k = 0; k < left; k++) {
-        const int rc = enqueue_step(c, c->timing);
+        const bool timed = c->timing && (c->timing_step++ % c->timing_every) == 0;
+        const int rc = enqueue_step(c, timed);
         if (rc != LBM_OK) return rc;
     }
     return LBM_OK;
@@ -918,9 +921,12 @@ LBM_API int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph) {
     return LBM_OK;
 }
 
-LBM_API int lbm_timing(lbm_ctx *c, int32_t enable) {
+LBM_API int lbm_timing(lbm_ctx *c, int32_t every) {
     if (!c) return LBM_EINVAL;
-    c->timing = enable != 0;
+    if (every < 0) return fail(c, LBM_EINVAL, "timing interval must be >= 0");
+    c->timing = every != 0;
+    c->timing_every = every > 0 ? every : 1;
+    c->timing_step = 0;
     c->ev_used = 0;
     return LBM_OK;
 }

@@ -122,8 +122,10 @@ class Simulation:
     def set_graph(self, steps_per_graph: int):
         self._check(self._lib.lbm_set_graph(self._ctx, int(steps_per_graph)))
 
-    def timing(self, enable: bool):
-        self._check(self._lib.lbm_timing(self._ctx, int(bool(enable))))
+    def timing(self, every):
+        """Main-kernel timing: False / 0 off, True / 1 every plain step, k:
+        every k-th plain step (lbm_timing)."""
+        self._check(self._lib.lbm_timing(self._ctx, int(every)))
 
     def timing_read(self):
         ms, n = C.c_double(), C.c_int64()

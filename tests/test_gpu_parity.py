@@ -208,6 +208,23 @@ def test_ensemble_of_uneven_replicas(Sim):
         compare(sim, r, 1e-12, rep=k, what=f"ensemble replica {k}")
 
 
+def test_timing_samples_every_kth_step(Sim):
+    from paper_1909_01092_amd._capi import LbmError
+    sim = Sim(workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 5e-5)), "fp32")
+    sim.timing(3)
+    sim.step(9)
+    ms, n = sim.timing_read()
+    assert n == 3 and ms > 0.0
+    sim.timing(1)
+    sim.step(4)
+    assert sim.timing_read()[1] == 4
+    sim.timing(0)
+    sim.step(2)
+    assert sim.timing_read()[1] == 0
+    with pytest.raises(LbmError):
+        sim.timing(-1)
+
+
 def test_many_replicas_finish_apart_fp64(Sim):
     """Forty replicas, enough particle workgroups (273) that the step is
     finished by its own launch rather than by the last workgroup: every
