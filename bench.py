@@ -272,6 +272,55 @@ def wetting_study(torch, steps=30000, tail=10000, every=500):
             "MLUPS": round(nodes * steps / el / 1e6, 1), "rows": rows, "drho_for_theta": calib}
 
 
+def interface_study(torch, steps=30000, tail=10000, every=500):
+    """A sphere at a flat interface pushed towards the A phase by a body force
+    (the paper's suggested follow-up: settling at the interface between two
+    immiscible fluids), for the paper's three wettabilities.  A trapped sphere
+    settles where capillarity balances F_ext; its offset from the interface,
+    z_i - Z, is averaged over the last `tail` steps.  A sphere whose centre
+    gets more than R + 2 below the interface plane has detached and sinks into
+    A (it then reaches the bottom wall, which ends that replica)."""
+    import numpy as np
+    from paper_1909_01092_amd import workloads as w
+    from paper_1909_01092_amd.sim import Simulation
+    reps = w.interface_trap()
+    sim = Simulation(reps, precision="fp32", device="cuda:0", stream=torch.cuda.Stream())
+    z0 = (w.WETTING_N - 1) / 2.0
+    detached = [None] * len(reps)
+    h = [[] for _ in reps]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        sim.step(every)
+        done += every
+        for r, q in enumerate(reps):
+            if detached[r] is not None:
+                continue
+            st = sim.particle_state(r, allow_unstable=True)
+            if st["unstable"] or st["X"][2] < z0 - q["radius"] - 2.0:
+                detached[r] = done
+            elif done > steps - tail:
+                rho, _ = sim.fields(r)
+                h[r].append(interface_height(rho, st["X"], q["radius"] + 8.0) - st["X"][2])
+    sim.sync()
+    el = time.perf_counter() - t0
+    rows = []
+    for r, q in enumerate(reps):
+        row = {"wettability": q["wettability"], "drho": q["wet_drho"], "F_ext": q["force"],
+               "detached_by_step": detached[r]}
+        if detached[r] is None:
+            d = np.array(h[r])
+            row.update({"zi_minus_Z": float(d.mean()), "spread": float(d.std())})
+        rows.append(row)
+    nodes = sum(q["nx"] * q["ny"] * q["nz"] for q in reps)
+    sim.close()
+    return {"study": "sphere at a flat interface under a body force towards A, kT = 0",
+            "box": f"{w.WETTING_N}^3 closed, R = {w.WETTING_R:g}, rho {w.PAPER_RHO0}", "steps": steps,
+            "averaged_over_last": tail, "seconds": round(el, 3), "MLUPS": round(nodes * steps / el / 1e6, 1),
+            "rows": rows}
+
+
 def langevin_stats(sim, reps, steps, skip):
     """Per-replica mean and variance of the particle velocity U_z over the
     last steps - skip recorded steps, grouped by lattice size, with the
@@ -377,10 +426,11 @@ def main():
                     help="instead of timing: run the large workload for STEPS steps in FP16 and in "
                          "FP32 storage on the same noise and report the FP16 error of the mean "
                          "velocity profile and of the particle velocity variance")
-    ap.add_argument("--study", default="", choices=["", "friction", "wetting"],
+    ap.add_argument("--study", default="", choices=["", "friction", "wetting", "interface"],
                     help="instead of timing: run a physics study and print its table (friction: "
                          "deterministic confinement friction c_m(d/L) at kT = 0; wetting: contact "
-                         "angle against Delta rho of a sphere at a flat interface)")
+                         "angle against Delta rho of a sphere at a flat interface; interface: that "
+                         "sphere under a body force, trapped or detached, for three wettabilities)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the step: time a plain device copy of this many MiB "
                          "(calibrates the HBM byte counters)")
@@ -402,6 +452,9 @@ def main():
         return
     if args.study == "wetting":
         print(json.dumps(wetting_study(torch, steps=args.steps or 30000)), flush=True)
+        return
+    if args.study == "interface":
+        print(json.dumps(interface_study(torch, steps=args.steps or 30000)), flush=True)
         return
     if args.workload == "adjoint":
         adjoint_bench(torch, args, args.steps or 1000)

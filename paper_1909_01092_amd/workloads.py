@@ -108,3 +108,27 @@ def wetting(drhos=WETTING_DRHO, n: int = WETTING_N, radius: float = WETTING_R,
                       init_split=n // 2, rho_p=2.0 * rho_tot, kT=0.0, radius=radius, wet_drho=d,
                       seed=0, replica=k, series_cap=steps_cap))
             for k, d in enumerate(drhos)]
+
+
+# the paper's three particle wettabilities (Sec. 3: theta_A = 120.5, 90 and 55
+# degrees) as wetting offsets for an R = 8 sphere, read off the contact-angle
+# sweep above (bench.py --study wetting)
+PAPER_WETTING_DRHO = {"hydrophobic": -0.146, "neutral": 0.0, "hydrophilic": 0.167}
+INTERFACE_FORCES = (0.0, 0.5, 1.0, 2.0, 3.0)
+
+
+def interface_trap(forces=INTERFACE_FORCES, n: int = WETTING_N, radius: float = WETTING_R,
+                   steps_cap: int = 16384) -> list:
+    """The contact-angle box with a body force pushing the sphere towards the A
+    phase (-z): F_ext = V (rho_p - rho_tot) g (Sec. 3 eq. fp) equal to each of
+    `forces`, for each of the paper's three wettabilities."""
+    import math
+    rho_tot = PAPER_RHO0[0] + PAPER_RHO0[1]
+    V = 4.0 / 3.0 * math.pi * radius ** 3
+    reps = []
+    for name, d in PAPER_WETTING_DRHO.items():
+        for F in forces:
+            q = wetting(drhos=(d,), n=n, radius=radius, steps_cap=steps_cap)[0]
+            g = F / (V * (q["rho_p"] - rho_tot))
+            reps.append(dict(q, g=(0.0, 0.0, -g), replica=len(reps), wettability=name, force=F))
+    return reps

@@ -13,6 +13,11 @@ surface at the contact angle: cos theta_A = (z_i - Z) / R.
     hydrophobic one (120.5 deg) at Delta rho < 0.
 The values of Delta rho themselves are not pinned: the paper does not print
 them, and they depend on the sphere's lattice resolution.
+
+The same sphere pushed towards the A phase by a body force (the paper's
+suggested follow-up, a particle settling at a fluid interface), for the three
+wettabilities: a trapped sphere moves further into A as the force grows, and
+the hydrophilic sphere, already deep in A, detaches first.
 """
 import os
 import sys
@@ -82,3 +87,36 @@ def test_contact_angle_sweep(Sim):
     assert cal["55"] > 0.0 > cal["120.5"]
     assert abs(cal["90"]) < 0.02
     assert c.min() < np.cos(np.radians(120.5)) and c.max() > np.cos(np.radians(55.0))
+
+
+def test_sphere_trapped_at_interface_under_force(Sim):
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    out = bench.interface_study(torch, steps=30000)
+    R = workloads.WETTING_R
+    by = {}
+    for r in out["rows"]:
+        print(f"  {r['wettability']:11s} F {r['F_ext']:.1f}  "
+              + (f"z_i - Z {r['zi_minus_Z']:+.3f}" if r["detached_by_step"] is None
+                 else f"detached by step {r['detached_by_step']}"), flush=True)
+        by.setdefault(r["wettability"], []).append(r)
+    theta = {"hydrophobic": 120.5, "neutral": 90.0, "hydrophilic": 55.0}
+    first_detach = {}
+    for name, rows in by.items():
+        rows.sort(key=lambda r: r["F_ext"])
+        assert rows[0]["F_ext"] == 0.0 and rows[0]["detached_by_step"] is None
+        # at rest on the interface: the calibrated contact angle, to the
+        # lattice pinning of the staircase sphere
+        assert abs(rows[0]["zi_minus_Z"] / R - np.cos(np.radians(theta[name]))) < 0.12
+        trapped = [r for r in rows if r["detached_by_step"] is None]
+        off = np.array([r["zi_minus_Z"] for r in trapped])
+        assert np.all(np.diff(off) > -0.1), (name, off)
+        assert off[-1] - off[0] > 1.0
+        det = [r["F_ext"] for r in rows if r["detached_by_step"] is not None]
+        first_detach[name] = min(det) if det else np.inf
+        # once detached at some force, every larger force detaches too
+        assert all(r["detached_by_step"] is not None for r in rows if r["F_ext"] >= first_detach[name])
+    assert first_detach["hydrophilic"] <= first_detach["neutral"] <= first_detach["hydrophobic"]
+    assert np.isfinite(first_detach["hydrophilic"])
+    assert first_detach["neutral"] > 1.0 and first_detach["hydrophobic"] > 1.0
