@@ -636,9 +636,9 @@ __device__ __forceinline__ T store_round(double v, T inv_scale, T scale, S &sv) 
 }
 
 // Mean post-streaming density of the neighbours of p that are fluid at X^n
-// and at X^{n+1} (raw of the box at orgo); rho0 when there is none.  Out of
-// line (it runs only next to uncovered nodes), with every argument passed by
-// value so that the caller keeps nothing in scratch memory for the call.
+// and at X^{n+1} (raw of the box at orgo); rho0 when there is none.  Every
+// argument is passed by value, so that no caller keeps its locals in scratch
+// memory for the call.
 struct Rho2 {
     double a, b;
 };
@@ -649,7 +649,7 @@ struct Org3 {
     int32_t v[3];
 };
 
-__device__ __noinline__ Rho2 mean_kept(int px, int py, int pz, Pos3 Xo, Pos3 Xn, double R2,
+__device__ __forceinline__ Rho2 mean_kept(int px, int py, int pz, Pos3 Xo, Pos3 Xn, double R2,
                                         const double *raw, Org3 orgo, int Sx, int S3, Geo g,
                                         double rho0A, double rho0B) {
     const int p[3] = {px, py, pz};
