@@ -38,6 +38,17 @@ PARITY_SMALL_STEPS = 200
 SINGLE_RUN = channel(64, 256, kT=1e-5, radius=8.0, g=(0.0, 0.0, 1e-4), seed=1, series_cap=16384)
 SINGLE_RUN_STEPS = 10000
 
+# the single run's parameter grid: kT x g x Delta rho, one replica each
+GRID_KT = (1e-6, 1e-5, 1e-4)
+GRID_G = (1e-5, 3e-5, 1e-4)
+GRID_DRHO = (-0.5, 0.0, 0.5)
+
+
+def single_grid(steps_cap: int = 4096) -> list:
+    return [dict(SINGLE_RUN, kT=kT, g=(0.0, 0.0, g), wet_drho=d, replica=k, series_cap=steps_cap,
+                 grid=(kT, g, d))
+            for k, (kT, g, d) in enumerate((kT, g, d) for kT in GRID_KT for g in GRID_G for d in GRID_DRHO)]
+
 
 def ensemble(steps_cap: int = 8192) -> list:
     """128 replicas of 32x32x128 (R = 4), 32 of 24x24x96 (R = 3), 32 of 48x48x192
