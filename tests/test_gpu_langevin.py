@@ -1,6 +1,7 @@
 """Statistics of the particle velocity over an ensemble of noise replicas,
 against the Langevin picture the paper verifies (Sec. 3, Langevin section):
-in the steady state Var(U) = kT / m_p whatever kT, the standardized
+in the steady state Var(U) = kT / m_p whatever kT, sphere size and driving
+(Delta U = sqrt(6 kT / (pi rho_p L^3)) (d/L)^(-3/2)), the standardized
 velocity is Gaussian, and the mean settling velocity does not depend on kT.  These run the HIP path only; the expected values are the
 closed forms, not the oracle.
 
@@ -75,3 +76,52 @@ def test_standardized_velocity_is_gaussian(series):
     skew, kurt = float((x ** 3).mean()), float((x ** 4).mean())
     print(f"standardized U_z: skewness {skew:.3f}, kurtosis {kurt:.3f}", flush=True)
     assert abs(skew) < 0.1 and abs(kurt - 3.0) < 0.3
+
+
+# ---- confinement scaling: Delta U = sqrt(6 kT / (pi rho_p L^3)) (d/L)^(-3/2)
+# (Sec. 3: Var(U) = kT / m_p with m_p = pi d^3 rho_p / 6), whatever the driving
+SIZES = (3.0, 4.0, 6.0, 8.0)     # d/L = 0.19 ... 0.5 in the 32 x 32 x 128 channel
+KT_S, G_S, G_HI, NREP_S = 1e-4, 5e-5, 2e-4, 16
+
+
+@pytest.fixture(scope="module")
+def size_series():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_01092_amd.sim import Simulation
+    cases = [(R_, G_S) for R_ in SIZES] + [(4.0, G_HI)]
+    reps = []
+    for R_, g in cases:
+        for k in range(NREP_S):
+            reps.append(workloads.channel(N, NZ, kT=KT_S, radius=R_, g=(0, 0, g), seed=37,
+                                          replica=len(reps), series_cap=STEPS))
+    sim = Simulation(reps, "fp32", stream=torch.cuda.Stream())
+    sim.step(STEPS)
+    assert not any(sim.particle_state(r)["unstable"] for r in range(len(reps)))
+    U = np.stack([sim.u_series(r)[SKIP:, 2] for r in range(len(reps))])
+    sim.close()
+    out = {}
+    for c, key in enumerate(cases):
+        u = U[c * NREP_S:(c + 1) * NREP_S]
+        out[key] = float(u.var(axis=1).mean())
+    return out
+
+
+def test_velocity_fluctuation_scales_with_confinement(size_series):
+    rho_p = 2.0
+    dl = np.array([2 * R_ / N for R_ in SIZES])
+    dU = np.array([math.sqrt(size_series[(R_, G_S)]) for R_ in SIZES])
+    pred = math.sqrt(6.0 * KT_S / (math.pi * rho_p * N ** 3)) * dl ** -1.5
+    for x, a, b in zip(dl, dU, pred):
+        print(f"d/L {x:.3f}: Delta U {a:.4e}, prediction {b:.4e}, ratio {a / b:.3f}", flush=True)
+    assert np.all(np.abs(dU / pred - 1.0) < 0.1)
+    slope = np.polyfit(np.log(dl), np.log(dU), 1)[0]
+    print(f"log-log slope of Delta U against d/L: {slope:.3f}", flush=True)
+    assert abs(slope + 1.5) < 0.1
+
+
+def test_velocity_fluctuation_independent_of_driving(size_series):
+    lo, hi = size_series[(4.0, G_S)], size_series[(4.0, G_HI)]
+    print(f"R = 4: Var(U_z) at g = {G_S:g}: {lo:.4e}, at g = {G_HI:g}: {hi:.4e}", flush=True)
+    assert abs(hi / lo - 1.0) < 0.15
