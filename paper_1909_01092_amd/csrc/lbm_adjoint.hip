@@ -814,7 +814,6 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
         const bool solid = near && solid_at(p[0], p[1], p[2], D, sn.org, sn.X, g, bs);
         const T G = T(D.G);
         T s[2] = {T(0), T(0)};
-#pragma unroll
         for (int i = 1; i < Q; i++) {
             const int c3[3] = {cx(i), cy(i), cz(i)};
             int pl[3];

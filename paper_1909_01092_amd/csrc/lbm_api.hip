@@ -275,7 +275,7 @@ int upload_desc(lbm_ctx *c) {
 }
 
 void drop_graph(lbm_ctx *c) {
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);  // teardown: nothing to report
     c->gexec = nullptr;
     c->graph_parity = -1;
 }
@@ -612,10 +612,10 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamEndCapture(c->stream, &graph);
                 c->cur = parity;  // capture only recorded the launches
-                if (rc != LBM_OK) { if (graph) hipGraphDestroy(graph); return rc; }
+                if (rc != LBM_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
                 if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
                 e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
-                hipGraphDestroy(graph);
+                (void)hipGraphDestroy(graph);  // the executable graph keeps what it needs
                 if (e != hipSuccess) { c->gexec = nullptr; return hip_fail(c, e, "hipGraphInstantiate"); }
                 c->graph_parity = parity;
             }
@@ -1098,13 +1098,14 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
 LBM_API void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     drop_graph(c);
+    // teardown: errors here have no caller to go to
     if (c->stream2) {
-        hipStreamSynchronize(c->stream2);
-        hipStreamDestroy(c->stream2);
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
     }
-    if (c->ev_fork) hipEventDestroy(c->ev_fork);
-    if (c->ev_join) hipEventDestroy(c->ev_join);
-    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
 
