@@ -95,7 +95,9 @@ typedef struct lbm_params {
     int32_t init_split;        /* 0: every node starts from rho0; k in [1, nz): nodes with */
                                /* z >= k start from the swapped pair (rho0[1], rho0[0]),   */
                                /* i.e. the other phase of a demixed mixture, which puts a  */
-                               /* flat A|B interface at z = k - 1/2                        */
+                               /* flat A|B interface at z = k - 1/2.  LBM_FP16 storage is  */
+                               /* relative to rho0, so it holds the swapped phase to about */
+                               /* 1e-3 of rho0[0] / rho0[1] only: use FP32 or FP64 there   */
 } lbm_params;
 
 /* Sphere state after the last completed step n. */

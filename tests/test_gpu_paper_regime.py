@@ -50,3 +50,32 @@ def test_paper_box_runs(Sim):
     assert not st["unstable"]
     assert np.all(np.abs(m1 - m0) <= 1e-5 * m0)
     assert st["U"][2] > 0
+
+
+def test_paper_box_langevin_statistics(Sim):
+    """The Langevin picture in the paper's own regime: 12 noise replicas of the
+    closed 60 x 60 x 900 box (rho 2.21 / 0.09, kT = 1e-4, R = 8), 5000 steps.
+    In the steady state the velocity variance along each axis is kT / m_p
+    (Sec. 3), the sphere settles along +g, and the standardized velocity is
+    Gaussian.  With a velocity relaxation time of about 100 steps, 12 x 4000
+    steps give a standard error of about 6% on the variance."""
+    import math
+    import torch
+    steps, skip, nrep = 5000, 1000, 12
+    reps = [dict(workloads.paper_box(steps_cap=steps), replica=k) for k in range(nrep)]
+    sim = Sim(reps, "fp32", stream=torch.cuda.Stream())
+    sim.step(steps)
+    assert not any(sim.particle_state(r)["unstable"] for r in range(nrep))
+    U = np.stack([sim.u_series(r)[skip:] for r in range(nrep)])
+    q = reps[0]
+    mp = 4.0 / 3.0 * math.pi * q["radius"] ** 3 * q["rho_p"]
+    ratios = [float(U[:, :, a].var(axis=1).mean() / (q["kT"] / mp)) for a in range(3)]
+    x = U[:, :, 2] - U[:, :, 2].mean(axis=1, keepdims=True)
+    x = (x / x.std(axis=1, keepdims=True)).ravel()
+    skew, kurt = float((x ** 3).mean()), float((x ** 4).mean())
+    print(f"paper box: Var(U)/(kT/m_p) = {ratios}, <U_z> = {U[:, :, 2].mean():.3e}, "
+          f"skewness {skew:.3f}, kurtosis {kurt:.3f}", flush=True)
+    for rt in ratios:
+        assert 0.85 < rt < 1.25
+    assert U[:, :, 2].mean() > 0
+    assert abs(skew) < 0.15 and abs(kurt - 3.0) < 0.4
