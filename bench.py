@@ -172,16 +172,18 @@ def adjoint_bench(torch, args, steps, segment=50):
     print(json.dumps(out), flush=True)
 
 
-def friction_study(torch, steps=12000, tail=1000):
+def friction_study(torch, steps=12000, tail=1000, wettability=False):
     """Deterministic confinement friction (kT = 0): terminal settling
     velocity of spheres of several d/L in the square channel, one replica per
     radius in one context, and the friction factor relative to Stokes,
     c_m = F_ext / (3 pi eta d U), F_ext = V (rho_p - rho_tot) g (Sec. 3 eq. fp),
-    eta = rho_tot nu, nu = (tau - 1/2) / 3."""
+    eta = rho_tot nu, nu = (tau - 1/2) / 3.  wettability: the paper's mixture
+    (rho 2.21 / 0.09) with each of its three wettabilities instead of the
+    0.95 / 0.05 mixture with a neutral sphere."""
     import math
     from paper_1909_01092_amd import workloads as w
     from paper_1909_01092_amd.sim import Simulation
-    reps = w.friction(steps_cap=steps)
+    reps = w.friction_wettability(steps_cap=steps) if wettability else w.friction(steps_cap=steps)
     sim = Simulation(reps, precision="fp32", device="cuda:0", stream=torch.cuda.Stream())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -196,12 +198,15 @@ def friction_study(torch, steps=12000, tail=1000):
         rho = q["rho0"][0] + q["rho0"][1]
         Fext = 4.0 / 3.0 * math.pi * R ** 3 * (q["rho_p"] - rho) * q["g"][2]
         eta = rho * (q["tau_shear"] - 0.5) / 3.0
-        rows.append({"R": R, "d_over_L": 2 * R / q["nx"], "U": float(U),
+        rows.append({"wettability": q.get("wettability", "neutral"), "drho": q["wet_drho"],
+                     "R": R, "d_over_L": 2 * R / q["nx"], "U": float(U),
                      "drift": float(abs(U - Uprev) / abs(U)), "c_m": float(Fext / (3 * math.pi * eta * 2 * R * U)),
                      "Re": float(abs(U) * 2 * R * 3.0 / (q["tau_shear"] - 0.5))})
     nodes = sum(q["nx"] * q["ny"] * q["nz"] for q in reps)
     sim.close()
-    return {"study": "confinement friction, kT = 0", "channel": f"{w.FRICTION_L}x{w.FRICTION_L}x{w.FRICTION_LZ}",
+    mix = f"rho {reps[0]['rho0'][0]:g} / {reps[0]['rho0'][1]:g}"
+    return {"study": "confinement friction, kT = 0", "mixture": mix,
+            "channel": f"{w.FRICTION_L}x{w.FRICTION_L}x{w.FRICTION_LZ}",
             "steps": steps, "mean_over_last": tail, "seconds": round(el, 3),
             "MLUPS": round(nodes * steps / el / 1e6, 1), "rows": rows}
 
@@ -426,9 +431,10 @@ def main():
                     help="instead of timing: run the large workload for STEPS steps in FP16 and in "
                          "FP32 storage on the same noise and report the FP16 error of the mean "
                          "velocity profile and of the particle velocity variance")
-    ap.add_argument("--study", default="", choices=["", "friction", "wetting", "interface"],
+    ap.add_argument("--study", default="", choices=["", "friction", "friction-wet", "wetting", "interface"],
                     help="instead of timing: run a physics study and print its table (friction: "
-                         "deterministic confinement friction c_m(d/L) at kT = 0; wetting: contact "
+                         "deterministic confinement friction c_m(d/L) at kT = 0; friction-wet: the "
+                         "same in the paper's mixture for its three wettabilities; wetting: contact "
                          "angle against Delta rho of a sphere at a flat interface; interface: that "
                          "sphere under a body force, trapped or detached, for three wettabilities)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -449,6 +455,10 @@ def main():
         return
     if args.study == "friction":
         print(json.dumps(friction_study(torch, steps=args.steps or 12000)), flush=True)
+        return
+    if args.study == "friction-wet":
+        print(json.dumps(friction_study(torch, steps=args.steps or 30000, tail=10000, wettability=True)),
+              flush=True)
         return
     if args.study == "wetting":
         print(json.dumps(wetting_study(torch, steps=args.steps or 30000)), flush=True)

@@ -143,3 +143,28 @@ def interface_trap(forces=INTERFACE_FORCES, n: int = WETTING_N, radius: float = 
             g = F / (V * (q["rho_p"] - rho_tot))
             reps.append(dict(q, g=(0.0, 0.0, -g), replica=len(reps), wettability=name, force=F))
     return reps
+
+
+
+# the same channels in the paper's mixture with its three wettabilities: radii
+# from d = 10 up (the paper resolves d >= 8); smaller non-neutral spheres
+# carry a minority-phase film whose flow outweighs this driving.  g is raised
+# so that the settling velocity stands above that flow (Re <= 0.06).
+FRICTION_WET_RADII = (5.0, 6.5, 8.0, 10.0)
+FRICTION_WET_G = 2e-5
+
+
+def friction_wettability(steps_cap: int = 32768, g: float = FRICTION_WET_G,
+                         radii=FRICTION_WET_RADII) -> list:
+    """The friction channels in the paper's mixture (rho 2.21 / 0.09, G = 1.5,
+    rho_p = 2 rho_tot) with each of its three wettabilities: one replica per
+    (wettability, radius)."""
+    rho_tot = PAPER_RHO0[0] + PAPER_RHO0[1]
+    reps = []
+    for name, d in PAPER_WETTING_DRHO.items():
+        for R in radii:
+            reps.append(channel(FRICTION_L, FRICTION_LZ, kT=0.0, init_amp=0.0, radius=R,
+                                g=(0.0, 0.0, g), rho0=PAPER_RHO0, rho_p=2.0 * rho_tot,
+                                wet_drho=d, seed=0, replica=len(reps), series_cap=steps_cap,
+                                wettability=name))
+    return reps

@@ -71,3 +71,28 @@ def test_confinement_friction_trend(Sim):
     slope = (cm - 1.0) / dl
     assert np.all(np.diff(slope) > 0)
     assert 0.5 < slope[0] < 4.0
+
+
+def test_friction_almost_independent_of_wettability(Sim):
+    """The paper's mixture (rho 2.21 / 0.09) with its three wettabilities
+    (Delta rho -0.146 / 0 / +0.167 for 120.5 / 90 / 55 degrees): the friction
+    factor barely depends on the wettability (the paper's friction figure),
+    and the neutral sphere's c_m is the miscible mixture's."""
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    wet = bench.friction_study(torch, steps=30000, tail=10000, wettability=True)
+    ref = {round(r["R"], 2): r["c_m"] for r in bench.friction_study(torch, steps=12000)["rows"]}
+    by = {}
+    for r in wet["rows"]:
+        print(f"  {r['wettability']:11s} d/L {r['d_over_L']:.3f}  c_m {r['c_m']:.3f}  drift {r['drift']:.1e}  "
+              f"Re {r['Re']:.1e}", flush=True)
+        by.setdefault(r["wettability"], {})[round(r["R"], 2)] = r
+        assert r["drift"] < 0.05 and r["Re"] < 0.1  # creeping flow: Oseen correction ~ 3 Re / 16
+    for name, rows in by.items():
+        cm = [rows[R]["c_m"] for R in sorted(rows)]
+        assert np.all(np.diff(cm) > 0), name
+    for R, r in by["neutral"].items():
+        assert abs(r["c_m"] / ref[R] - 1.0) < 0.03, (R, r["c_m"], ref[R])
+        for name in ("hydrophobic", "hydrophilic"):
+            assert abs(by[name][R]["c_m"] / r["c_m"] - 1.0) < 0.06, (name, R)
