@@ -45,7 +45,11 @@ def workspace_bytes(replicas, precision="fp64") -> int:
 class Simulation:
     """One or more replicas advanced together on one GPU."""
 
-    def __init__(self, replicas, precision: str = "fp64", device="cuda:0", stream=None):
+    def __init__(self, replicas, precision: str = "fp64", device="cuda:0", stream=None,
+                 fill=None):
+        """fill: a byte value written over the whole workspace before
+        lbm_init (0xff is a NaN in FP64, FP32 and FP16), so that a read of
+        memory no kernel wrote shows up in the results."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulation needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -56,6 +60,9 @@ class Simulation:
         self._params = make_params(self.replicas)
         nbytes = workspace_bytes(self.replicas, precision)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if fill is not None:
+            self.workspace.fill_(int(fill))
+            torch.cuda.synchronize(self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self._ws_bytes = nbytes

@@ -381,3 +381,29 @@ def test_ensemble_full_size_one_step_fp32(Sim):
         ref.set_particle({k: p0[k] for k in ("X", "U", "W", "Pev", "Lev", "step", "n_fluid")})
         ref.step(1)
         compare(sim, ref, 1e-7, 2e-5, rep=r, what=f"ensemble replica {r} one step from the GPU state")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_no_unwritten_memory_is_read(Sim, prec):
+    """Every slot a step pulls from has been written: with the workspace
+    filled with NaN bytes (0xff) before initialisation the run has no NaN and
+    is bitwise the run on a zero-filled workspace, through walls, periodic
+    wrap, a moving sphere with cover / uncover events and the wetting layer."""
+    import torch
+    reps = [workloads.channel(16, 24, kT=1e-5, radius=3.3, wet_drho=0.2, seed=8, replica=0,
+                              U0=(0.02, -0.01, 0.08)),
+            workloads.full(dict(nx=12, ny=14, nz=16, walls=7, kT=1e-5, init_amp=1e-3, G=1.5,
+                                radius=2.5, rho_p=2.0, wet_drho=-0.1, U0=(0.0, 0.03, -0.06),
+                                seed=8, replica=1))]
+    runs = []
+    for fill in (0xFF, 0x00):
+        sim = Sim(reps, prec, stream=torch.cuda.Stream(), fill=fill)
+        sim.step(30)
+        runs.append([(sim.populations(r), sim.particle_state(r)) for r in range(len(reps))])
+        sim.close()
+    for (fa, pa), (fb, pb) in zip(*runs):
+        assert not np.isnan(fa).any()
+        assert np.array_equal(fa, fb)
+        for k in ("X", "U", "W", "F", "T"):
+            assert np.array_equal(pa[k], pb[k])
+        assert pa["n_covered"] > 0 and pa["n_uncovered"] > 0
