@@ -407,3 +407,21 @@ def test_no_unwritten_memory_is_read(Sim, prec):
         for k in ("X", "U", "W", "F", "T"):
             assert np.array_equal(pa[k], pb[k])
         assert pa["n_covered"] > 0 and pa["n_uncovered"] > 0
+
+
+def test_poisoned_checkpoint_is_reported(Sim):
+    """A checkpoint whose population block carries NaN bytes restores, and the
+    next step sets the sticky unstable flag (LBM_EUNSTABLE on the state
+    query) instead of running on silently."""
+    from paper_1909_01092_amd import _capi
+    sim = Sim(workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 5e-5), seed=4), "fp32")
+    sim.step(5)
+    ck = sim.checkpoint()
+    mid = (ck.numel() // 2) // 256 * 256
+    ck[mid:mid + 4096].fill_(0xFF)
+    sim.restore(ck)
+    sim.particle_state()  # the restored state itself is not flagged yet
+    sim.step(1)
+    with pytest.raises(_capi.LbmError) as e:
+        sim.particle_state()
+    assert e.value.code == _capi.LBM_EUNSTABLE
