@@ -138,6 +138,23 @@ def test_fp32_parity_small_channel(Sim):
     assert errU < 1e-5 and errX < 1e-7
 
 
+def test_fp32_parity_single_run_slice(Sim):
+    """A 64 x 64 x 64 slice of the single-run channel (R = 8, kT = 1e-5,
+    g = 1e-4) in the benchmark's launch shape (full 64-node rows, 256 x 4):
+    60 FP32 steps against the oracle."""
+    p = dict(workloads.SINGLE_RUN, nz=64, X0=None)
+    p = workloads.full(p)
+    sim, ref = Sim(p, "fp32"), OracleSim(p)
+    sim.set_launch(256, 4)
+    sim.step(60)
+    ref.step(60)
+    compare(sim, ref, 1e-6, 1e-5, what="64x64x64 slice, fp32 60 steps")
+    pg, po = sim.particle_state(), ref.particle()
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    print(f"slice particle U rel err {errU:.3e}", flush=True)
+    assert errU < 1e-5
+
+
 def test_fp16_error_reported(Sim):
     p = workloads.PARITY_SMALL
     sim, ref = Sim(p, "fp16"), OracleSim(p)
