@@ -1161,8 +1161,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
     if (t != 0) return;
     st->k3_done = 0;
+    // the next launch sees these stores: kernel boundaries order them
     publish_step(a, D, st, g, sum, mo, tot);
-    __threadfence();
 }
 
 // ============================================================== k_finish
