@@ -180,8 +180,11 @@ int lbm_get_launch(lbm_ctx *c, int32_t *block, int32_t *zchunk);
 int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *block_out,
                  int32_t *zchunk_out, double *best_ms);
 
-/* 0: plain launches; k > 0: lbm_step replays a HIP graph of k steps (k even;
- * needs a non-default stream); leftover steps run as plain launches. */
+/* 0: plain launches; k > 0: lbm_step replays a HIP graph of k steps (needs a
+ * non-default stream); leftover steps run as plain launches, and so do all
+ * steps while lbm_timing is on.  An even k replays one captured graph; an
+ * odd k swaps the roles of the two population buffers at every replay, so
+ * the graph is captured again each time.  Results equal plain launches. */
 int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph);
 
 /* Overlapped steps (default off; needs a sphere in some replica and a
