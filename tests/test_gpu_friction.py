@@ -96,3 +96,35 @@ def test_friction_almost_independent_of_wettability(Sim):
         assert abs(r["c_m"] / ref[R] - 1.0) < 0.03, (R, r["c_m"], ref[R])
         for name in ("hydrophobic", "hydrophilic"):
             assert abs(by[name][R]["c_m"] / r["c_m"] - 1.0) < 0.06, (name, R)
+
+
+def test_mean_velocity_with_noise_is_the_deterministic_one(Sim):
+    """Sec. 3: with thermal fluctuations the mean settling velocity is still
+    F_p / gamma_conf, the deterministic friction's.  The paper's mixture at
+    d/L = 0.5 (R = 8 in the 32 x 32 x 128 channel) with each of its three
+    wettabilities: 8 noise replicas at kT = 1e-4 against the kT = 0 run.
+    With a velocity relaxation time of about 50 steps, 8 x 8000 steps give a
+    standard error near 1% of <U_z>.  Measured: +0.7% / +2.2% / +0.5% for the
+    hydrophobic / neutral / hydrophilic sphere; the bound is four standard
+    errors or 3%, whichever is larger (the paper states the agreement within
+    its error bars)."""
+    import torch
+    steps, skip, nrep = 10000, 2000, 8
+    base = [q for q in workloads.friction_wettability(steps_cap=steps, radii=(8.0,))]
+    reps = []
+    for q in base:
+        reps.append(dict(q, replica=len(reps)))
+        for k in range(nrep):
+            reps.append(dict(q, kT=1e-4, init_amp=1e-3, seed=50, replica=len(reps)))
+    sim = Sim(reps, "fp32", stream=torch.cuda.Stream())
+    sim.step(steps)
+    assert not any(sim.particle_state(r)["unstable"] for r in range(len(reps)))
+    U = np.stack([sim.u_series(r)[skip:, 2] for r in range(len(reps))])
+    for c, q in enumerate(base):
+        det = U[c * (nrep + 1)].mean()
+        means = U[c * (nrep + 1) + 1:(c + 1) * (nrep + 1)].mean(axis=1)
+        se = means.std(ddof=1) / np.sqrt(nrep)
+        print(f"  {q['wettability']:11s}: <U_z> kT=0 {det:.4e}, kT=1e-4 {means.mean():.4e} "
+              f"(+- {se:.1e})", flush=True)
+        assert abs(means.mean() - det) < max(4.0 * se, 0.03 * det)
+        assert se < 0.03 * det
