@@ -75,6 +75,25 @@ def traffic_from_profile(name, block, zchunk):
     return d.get("hbm_bytes_per_launch")
 
 
+def plain_comparison(torch, mlups, steps=1000):
+    """The batched form against the plain single-run path: MLUPS of the
+    64x64x256 single run (autotuned, plain launches) timed here, and the
+    ratio of the batched throughput to it."""
+    from paper_1909_01092_amd.sim import Simulation
+    reps, prec, _ = workload("single")
+    sim = Simulation(reps, precision=prec, device="cuda:0", stream=torch.cuda.Stream())
+    sim.autotune(steps_per_trial=10, preserve=False)
+    sim.step(100)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    el = time.perf_counter() - t0
+    sim.close()
+    plain = reps[0]["nx"] * reps[0]["ny"] * reps[0]["nz"] * steps / el / 1e6
+    return {"plain_single_run_MLUPS": round(plain, 1), "batched_over_plain": round(mlups / plain, 3)}
+
+
 def cpu_baseline(reps, budget_s=15.0):
     """FP64 oracle on the first replica of the workload, whole steps until the
     budget is spent (at least one step)."""
@@ -526,6 +545,8 @@ def main():
         out["langevin"] = stats
     sim.close()
     del sim
+    if args.workload == "ensemble":
+        out["vs_plain"] = plain_comparison(torch, mlups)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(reps)
     print(json.dumps(out), flush=True)
