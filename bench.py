@@ -410,9 +410,12 @@ def fp16_error(torch, steps, every=50, skip=500):
 
 
 def copy_calibration(torch, mib, steps, warmup):
-    """Plain device-to-device copy of `mib` MiB: its duration gives a copy
-    ceiling, and under rocprofv3 its FETCH_SIZE / WRITE_SIZE per dispatch give
-    the scale between those counters and bytes actually moved."""
+    """Plain device-to-device copy of `mib` MiB (the runtime's copy kernel):
+    under rocprofv3 its FETCH_SIZE / WRITE_SIZE per dispatch give the scale
+    between those counters and bytes actually moved.  Also timed: a streaming
+    elementwise kernel (dst = src * 1, one read and one write per element),
+    the faster of the two and the bandwidth ceiling quoted for read + write
+    kernels."""
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
@@ -427,8 +430,19 @@ def copy_calibration(torch, mib, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     moved = 2 * n * 4
+    for _ in range(max(warmup, 1)):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1) / steps
     print(json.dumps({"copy_mib": mib, "ms_per_copy": round(ms, 5), "bytes_moved": moved,
-                      "GB/s": round(moved / (ms * 1e-3) / 1e9, 1)}), flush=True)
+                      "GB/s": round(moved / (ms * 1e-3) / 1e9, 1),
+                      "stream_ms": round(ms_s, 5), "stream_GB/s": round(moved / (ms_s * 1e-3) / 1e9, 1)}),
+          flush=True)
 
 
 def main():
