@@ -397,7 +397,7 @@ def fp16_error(torch, steps, every=50, skip=500):
         sim.close()
         del sim
     a, b = res["fp16"], res["fp32"]
-    print(json.dumps({
+    return {
         "workload": "large 192x192x1024, R=16, kT=1e-4, g=1e-4, G=1.5", "steps": steps,
         "reference": "fp32 storage (same noise)",
         "uz_profile_rel_l2": float(np.linalg.norm(a["profile"] - b["profile"]) / np.linalg.norm(b["profile"])),
@@ -406,7 +406,7 @@ def fp16_error(torch, steps, every=50, skip=500):
         "mean_Uz_rel": abs(a["mean"] - b["mean"]) / abs(b["mean"]),
         "U_end_rel": abs(a["U_end"] - b["U_end"]) / abs(b["U_end"]),
         "seconds": {"fp32": round(b["sec"], 1), "fp16": round(a["sec"], 1)},
-        "unstable": bool(a["unstable"] or b["unstable"])}), flush=True)
+        "unstable": bool(a["unstable"] or b["unstable"])}
 
 
 def copy_calibration(torch, mib, steps, warmup):
@@ -484,7 +484,7 @@ def main():
         copy_calibration(torch, args.copy_mib, args.steps or 2000, args.warmup)
         return
     if args.fp16_error:
-        fp16_error(torch, args.fp16_error)
+        print(json.dumps(fp16_error(torch, args.fp16_error)), flush=True)
         return
     if args.study == "friction":
         print(json.dumps(friction_study(torch, steps=args.steps or 12000)), flush=True)

@@ -464,3 +464,21 @@ def test_contexts_are_independent(Sim):
     for s, (f, X) in zip((a, b), alone):
         assert np.array_equal(s.populations(), f)
         assert np.array_equal(s.particle_state()["X"], X)
+
+
+def test_fp16_storage_error_on_the_large_channel(Sim):
+    """The large channel (192 x 192 x 1024, R = 16, kT = 1e-4) for 2000 steps
+    with FP16 relative-deviation storage against FP32 storage on the same
+    noise: the time-averaged u_z(x, y) profile, the particle's mean velocity
+    and its velocity variance (measured 3e-4, 4e-6 and 3e-5)."""
+    import os
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    out = bench.fp16_error(torch, 2000)
+    print({k: out[k] for k in ("uz_profile_rel_l2", "mean_Uz_rel", "var_Uz_rel", "unstable")}, flush=True)
+    assert not out["unstable"]
+    assert out["uz_profile_rel_l2"] < 2e-3
+    assert out["mean_Uz_rel"] < 1e-4
+    assert out["var_Uz_rel"] < 1e-3
