@@ -29,6 +29,7 @@
 // wetting-reaction terms of the sphere links), and k_adj_chain over the box
 // (wetting-layer chain; its last workgroup makes the fixed-order sums into
 // the adjoint state).
+#include <utility>
 #include "lbm_adjoint.h"
 #include "lbm_kernels_impl.h"
 
@@ -36,6 +37,12 @@ namespace lbm {
 namespace {
 
 constexpr int NB = 256;  // node-kernel block
+
+// f(integral_constant<int, i>) for i = 1 .. Q - 1, in that order
+template <typename F, int... I>
+__device__ __forceinline__ void for_each_dir(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I + 1>{}), ...);
+}
 
 __device__ __forceinline__ bool solid_at(int x, int y, int z, const RepDesc &D, const int32_t *org,
                                          const double *X, const Geo &g, int &b) {
@@ -814,21 +821,29 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
         const bool solid = near && solid_at(p[0], p[1], p[2], D, sn.org, sn.X, g, bs);
         const T G = T(D.G);
         T s[2] = {T(0), T(0)};
-        for (int i = 1; i < Q; i++) {
+        // every direction expanded at compile time (in ascending order, as a
+        // loop would add them): the subsets m that use an axis the direction
+        // does not move along drop out, and the loads of the remaining
+        // candidates are issued together
+        auto dir_term = [&](auto ic) {
+            constexpr int i = decltype(ic)::value;
             const int c3[3] = {cx(i), cy(i), cz(i)};
             int pl[3];
             bool cl[3];
+#pragma unroll
             for (int ax = 0; ax < 3; ax++) {
                 int v = p[ax] - c3[ax];
                 if (!w3[ax]) v = v < 0 ? v + n3[ax] : (v >= n3[ax] ? v - n3[ax] : v);
                 pl[ax] = v;
                 cl[ax] = w3[ax] && ((c3[ax] == -1 && p[ax] == 0) || (c3[ax] == 1 && p[ax] == n3[ax] - 1));
             }
-            if (!(cl[0] || cl[1] || cl[2])) continue;
+            if (!(cl[0] || cl[1] || cl[2])) return;
             const T w = T(wgt(i));
+#pragma unroll
             for (int m = 1; m < 8; m++) {
                 int xs[3];
                 bool ok = true;
+#pragma unroll
                 for (int ax = 0; ax < 3; ax++) {
                     const bool use = (m >> ax) & 1;
                     if (use && !cl[ax]) ok = false;
@@ -850,7 +865,8 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
                 s[1] += -G * rA * w * cFA;
                 s[0] += -G * rB * w * cFB;
             }
-        }
+        };
+        for_each_dir(dir_term, std::make_integer_sequence<int, Q - 1>{});
         if (!solid) {
             const int64_t m = lin(p, g);
             const T v0 = A0[m] + s[0], v1 = A0[N + m] + s[1];
