@@ -1,0 +1,63 @@
+"""Host side of the benchmark (no GPU): the one-GPU guard and the committed
+main-kernel counter summaries that give the bench line its measured HBM
+traffic."""
+import glob
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
+COUNTER_FILES = sorted(glob.glob(os.path.join(ROOT, "profiles", "k_main_*_counters.json")))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_summaries_exist():
+    names = {os.path.basename(p)[len("k_main_"):-len("_counters.json")] for p in COUNTER_FILES}
+    assert "single" in names
+
+
+@pytest.mark.parametrize("path", COUNTER_FILES, ids=lambda p: os.path.basename(p))
+def test_counter_summary_consistent(path):
+    with open(path) as fh:
+        d = json.load(fh)
+    name = d["workload"]
+    assert os.path.basename(path) == f"k_main_{name}_counters.json"
+    assert glob.glob(os.path.join(ROOT, "profiles", f"k_main_{name}_*counters.md"))
+    # HBM bytes per launch = scaled FETCH_SIZE + scaled WRITE_SIZE (KiB)
+    hbm = (d["fetch_kib_per_dispatch"] * d["fetch_scale"] + d["write_kib_per_dispatch"] * d["write_scale"]) * 1024
+    assert abs(hbm - d["hbm_bytes_per_launch"]) <= 1e-3 * hbm
+    # a launch reads and writes every population at least once
+    reps, prec, _ = bench.workload(name)
+    nodes = sum(p["nx"] * p["ny"] * p["nz"] for p in reps)
+    algorithmic = nodes * 2 * 19 * 2 * STORE_BYTES[prec]
+    assert d["hbm_bytes_per_launch"] >= 0.95 * algorithmic
+    assert d["hbm_bytes_per_launch"] <= 3.0 * algorithmic
+    assert all("rocprofv3 --pmc" in c and "bench.py" in c for c in d["commands"])
+
+
+@pytest.mark.parametrize("path", COUNTER_FILES, ids=lambda p: os.path.basename(p))
+def test_traffic_only_for_the_profiled_shape(path):
+    with open(path) as fh:
+        d = json.load(fh)
+    name, block, cz = d["workload"], d["block"], d["zchunk"]
+    assert bench.traffic_from_profile(name, block, cz + 1) is None
+    other = 512 if block != 512 else 256
+    assert bench.traffic_from_profile(name, other, cz) is None
+    got = bench.traffic_from_profile(name, block, cz)
+    if d["kernel_hash"] == bench.kernel_hash():
+        assert got == d["hbm_bytes_per_launch"]
+    else:  # counters taken on other kernel sources are not reported
+        assert got is None
