@@ -61,3 +61,13 @@ def test_traffic_only_for_the_profiled_shape(path):
         assert got == d["hbm_bytes_per_launch"]
     else:  # counters taken on other kernel sources are not reported
         assert got is None
+
+
+def test_cpu_baseline_leg():
+    reps, prec, _ = bench.workload("parity")
+    cb = bench.cpu_baseline(reps, budget_s=0.5)
+    assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
+    assert cb["unit"] == "MLUPS" and cb["kind"] == "oracle" and cb["cores"] == 1
+    assert cb["value"] > 0.0
+    p = reps[0]
+    assert f"{p['nx']}x{p['ny']}x{p['nz']}" in cb["sample"] and "FP64" in cb["sample"]
