@@ -64,15 +64,19 @@ def workload(name):
 def traffic_from_profile(name, block, zchunk):
     """HBM bytes per launch of the main kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel sources in the
-    same launch shape."""
+    same launch shape (the summary's own shape, or one of its per-shape
+    entries)."""
     path = os.path.join(ROOT, "profiles", f"k_main_{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != kernel_hash() or d.get("block") != block or d.get("zchunk") != zchunk:
+    if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    for e in [d] + d.get("shapes", []):
+        if e.get("block") == block and e.get("zchunk") == zchunk:
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def plain_comparison(torch, mlups, steps=1000):

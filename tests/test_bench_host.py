@@ -46,21 +46,28 @@ def test_counter_summary_consistent(path):
     assert d["hbm_bytes_per_launch"] >= 0.95 * algorithmic
     assert d["hbm_bytes_per_launch"] <= 3.0 * algorithmic
     assert all("rocprofv3 --pmc" in c and "bench.py" in c for c in d["commands"])
+    for e in d.get("shapes", []):
+        hbm = (e["fetch_kib_per_dispatch"] * d["fetch_scale"] + e["write_kib_per_dispatch"] * d["write_scale"]) * 1024
+        assert abs(hbm - e["hbm_bytes_per_launch"]) <= 1e-3 * hbm
+        assert algorithmic * 0.95 <= e["hbm_bytes_per_launch"] <= 3.0 * algorithmic
 
 
 @pytest.mark.parametrize("path", COUNTER_FILES, ids=lambda p: os.path.basename(p))
 def test_traffic_only_for_the_profiled_shape(path):
     with open(path) as fh:
         d = json.load(fh)
-    name, block, cz = d["workload"], d["block"], d["zchunk"]
-    assert bench.traffic_from_profile(name, block, cz + 1) is None
-    other = 512 if block != 512 else 256
-    assert bench.traffic_from_profile(name, other, cz) is None
-    got = bench.traffic_from_profile(name, block, cz)
-    if d["kernel_hash"] == bench.kernel_hash():
-        assert got == d["hbm_bytes_per_launch"]
-    else:  # counters taken on other kernel sources are not reported
-        assert got is None
+    name = d["workload"]
+    profiled = {(d["block"], d["zchunk"]): d["hbm_bytes_per_launch"]}
+    for e in d.get("shapes", []):
+        profiled.setdefault((e["block"], e["zchunk"]), e["hbm_bytes_per_launch"])
+    current = d["kernel_hash"] == bench.kernel_hash()
+    for block in (256, 512, 1024):
+        for cz in (1, 2, 3, 4, 8, 16, 32):
+            got = bench.traffic_from_profile(name, block, cz)
+            if current and (block, cz) in profiled:
+                assert got == profiled[(block, cz)]
+            else:  # another shape, or counters taken on other kernel sources
+                assert got is None
 
 
 def test_cpu_baseline_leg():
