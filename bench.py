@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--workload", default="single")
     ap.add_argument("--zchunk", type=int, default=0, help="fixed main-kernel z-chunk (skips the autotuner)")
     ap.add_argument("--block", type=int, default=256, help="main-kernel block with --zchunk")
-    ap.add_argument("--autotune", type=int, default=20,
+    ap.add_argument("--autotune", type=int, default=100,
                     help="steps per candidate of the launch-shape autotuner (0: library default shape)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: plain launches)")
     ap.add_argument("--no-cpu", action="store_true")
