@@ -58,7 +58,7 @@ struct AdjArgs {
     const void *recn1;       // moments after step n
     void *Anext;             // adjoint of the state after step n: [8][N] (rho_A, rho_B, j_A, j_B)
     void *Acur;              // adjoint of the state before step n, written
-    void *Fb;                // adjoint of the node forces of step n: [6][N]
+    void *Fb;                // rho_l(x) times the adjoint of the node force F_l(x) of step n: [6][N]
     double *vt;              // box of X^n: wetting-layer densities of step n [2][S^3]
     double *vinv;            // box: 1 / fluid-neighbour count of particle nodes (0: none) [S^3]
     double *vtb;             // box: adjoint of the wetting-layer densities [2][S^3]

@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             A0[l * N + n] = rb[l];
             for (int q = 0; q < 3; q++) {
                 A0[(2 + 3 * l + q) * N + n] = jb[q];
-                Fo[(3 * l + q) * N + n] = Fbv[l][q];
+                Fo[(3 * l + q) * N + n] = f.rl[l] * Fbv[l][q];
             }
         }
     }
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(NB) void k_adj_links(AdjArgs a) {
                 A0[c * N + n] = T((double)A0[c * N + n] + out[c]);
                 for (int q = 0; q < 3; q++) {
                     A0[(2 + 3 * c + q) * N + n] += T(out[2 + q]);
-                    Fo[(3 * c + q) * N + n] += T(out[5 + 3 * c + q]);
+                    Fo[(3 * c + q) * N + n] += f.rl[c] * T(out[5 + 3 * c + q]);
                 }
             }
         }
@@ -733,15 +733,16 @@ __global__ __launch_bounds__(NB) void k_adj_gather(AdjArgs a) {
             if (near && solid_at(xs[0], xs[1], xs[2], D, sn.org, sn.X, g, bx)) return;
             const int64_t si = lin(xs, g);
             const T w = T(wgt(i));
-            const T rA = T(D.rho0[0]) + rec[si], rB = T(D.rho0[1]) + rec[N + si];
+            // Fb holds rho_l(x) times the force adjoint of x
             T cFA = T(0), cFB = T(0);
             if (cx(i)) { cFA += cx(i) > 0 ? Fb[si] : -Fb[si]; cFB += cx(i) > 0 ? Fb[3 * N + si] : -Fb[3 * N + si]; }
             if (cy(i)) { cFA += cy(i) > 0 ? Fb[N + si] : -Fb[N + si]; cFB += cy(i) > 0 ? Fb[4 * N + si] : -Fb[4 * N + si]; }
             if (cz(i)) { cFA += cz(i) > 0 ? Fb[2 * N + si] : -Fb[2 * N + si]; cFB += cz(i) > 0 ? Fb[5 * N + si] : -Fb[5 * N + si]; }
             // F_A(x) reads rho~_B(y), F_B(x) reads rho~_A(y)
-            s[1] += -G * rA * w * cFA;
-            s[0] += -G * rB * w * cFB;
+            s[1] += -G * w * cFA;
+            s[0] += -G * w * cFB;
             if (solid && !mirrored) {
+                const T rA = T(D.rho0[0]) + rec[si], rB = T(D.rho0[1]) + rec[N + si];
                 const double d3[3] = {sepd(xs[0] - sn.X[0], g.nx, g.wx), sepd(xs[1] - sn.X[1], g.ny, g.wy),
                                       sepd(xs[2] - sn.X[2], g.nz, g.wz)};
                 double TxD[3];
@@ -790,7 +791,6 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
     const Geo g = geo_of(D);
     const int64_t N = g.N;
     const int S3 = D.S * D.S * D.S;
-    const T *rec = static_cast<const T *>(a.recn);
     const T *Fb = static_cast<const T *>(a.Fb);
     T *A0 = static_cast<T *>(a.Acur);
     const int n3[3] = {g.nx, g.ny, g.nz};
@@ -854,16 +854,15 @@ __global__ __launch_bounds__(NB) void k_adj_mirror(AdjArgs a) {
                 int bx;
                 if (near && solid_at(xs[0], xs[1], xs[2], D, sn.org, sn.X, g, bx)) continue;
                 const int64_t si = lin(xs, g);
-                const T rA = T(D.rho0[0]) + rec[si], rB = T(D.rho0[1]) + rec[N + si];
-                T cFA = T(0), cFB = T(0);
+                T cFA = T(0), cFB = T(0);  // Fb holds rho_l(x) times the force adjoint of x
                 for (int q = 0; q < 3; q++) {
                     if (!c3[q]) continue;
                     const T fa = Fb[q * N + si], fb = Fb[(3 + q) * N + si];
                     cFA += c3[q] > 0 ? fa : -fa;
                     cFB += c3[q] > 0 ? fb : -fb;
                 }
-                s[1] += -G * rA * w * cFA;
-                s[0] += -G * rB * w * cFB;
+                s[1] += -G * w * cFA;
+                s[0] += -G * w * cFB;
             }
         };
         for_each_dir(dir_term, std::make_integer_sequence<int, Q - 1>{});
