@@ -111,7 +111,14 @@ typedef struct lbm_particle {
     int64_t n_covered, n_uncovered, n_links;
 } lbm_particle;
 
-/* Global observables of the current state of one replica. */
+/* Global observables of the current state of one replica: the fluid's
+ * per-component mass and momentum (the moments of eq. density, Sec. 2), the
+ * mean square of the hydrodynamic velocity v_H = v + (F_A + F_B)/(2 rho_tot)
+ * (Sec. 2, force paragraph) and the settling-direction profile of v_H,z over
+ * the channel cross-section, the fluid flow around the particle the set-up
+ * of Sec. 3 (Fig. 1 caption) drives.  Sums run over fluid nodes in a fixed
+ * order: per (x, y) column along z on the device, then the columns in order
+ * on the host. */
 typedef struct lbm_obs {
     double mass[2];            /* sum of rho_l over fluid nodes                            */
     double momentum[3];        /* sum of (j_A + j_B) over fluid nodes                      */
@@ -141,6 +148,10 @@ int lbm_step(lbm_ctx *c, int32_t nsteps);
 int lbm_sync(lbm_ctx *c);
 
 int lbm_particle_state(lbm_ctx *c, int32_t replica, lbm_particle *out);
+/* Fills *o; o->uz_profile, when not NULL, receives nx * ny values (row-major
+ * [y][x], a column with no fluid node gives 0).  Synchronises the context
+ * stream.  LBM_EINVAL for a bad replica or NULL o; LBM_EUNSTABLE (after
+ * filling *o) when the run went unstable. */
 int lbm_observables(lbm_ctx *c, int32_t replica, lbm_obs *o);
 
 /* f_{l i}(x, n) (after streaming and mass correction, particle nodes 0) of one
@@ -151,8 +162,14 @@ int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f);
  * host_rho[2][nz][ny][nx], host_u[3][nz][ny][nx]. */
 int lbm_fields(lbm_ctx *c, int32_t replica, double *host_rho, double *host_u);
 
-/* U^{n+1/2} of the last min(steps, series_cap) steps, oldest first, into
- * host_u3[k][3]; *count = number written. */
+/* The particle velocity time series the paper tracks (Fig. 1 caption) and
+ * whose mean and variance it analyses (Sec. 4, eq. MEANVARIANCE and eq.
+ * FLUCTUATIONSSCALING): U^{n+1/2} of each step, kept on the device in a ring
+ * of series_cap entries that the step writes at slot n mod series_cap.
+ * Copies the last min(steps, series_cap, cap) entries, oldest first, into
+ * host_u3[k][3] (caller-owned, 3 cap doubles); *count = number written.
+ * Synchronises the context stream.  LBM_EINVAL for a bad replica, NULL
+ * outputs or cap < 0. */
 int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t cap, int64_t *count);
 
 /* Checkpoint: the complete state needed to resume bit-for-bit. */
@@ -187,29 +204,17 @@ int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *b
  * the graph is captured again each time.  Results equal plain launches. */
 int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph);
 
-/* Overlapped steps (default off; needs a sphere in some replica and a
- * non-default context stream, otherwise the call keeps them off): the main
- * kernel runs as two launches of the same kernel, the tiles within one node
- * of a sphere's bounding box on the context stream, followed there by the
- * link and particle kernels, and all other tiles on a second library-owned
- * stream at the same time; the two streams join at the end of every step.
- * Results are identical either way.  Synchronises the context stream. */
-int lbm_set_overlap(lbm_ctx *c, int32_t enable);
-
 /* Timing of the main kernel.  every = 0 turns it off; every = k >= 1 makes
  * every k-th plain-launch step from now on (the first, the (k+1)-th, ...)
- * record HIP events around its main-kernel launch (its far-tile part when
- * steps are overlapped) on the stream it runs on.  A sparse sample keeps
+ * record HIP events around its main-kernel launch on the context stream.  A sparse sample keeps
  * the events' own cost out of the other steps.  lbm_timing_read returns the
  * mean duration (ms) and the number of timed launches since it was enabled.
  * EINVAL for every < 0. */
 int lbm_timing(lbm_ctx *c, int32_t every);
 int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count);
 
-/* Algorithmic bytes the timed main-kernel launch moves per step (read +
- * write of 2 x 19 populations per node it updates: every node, or the nodes
- * of the far tiles for the current sphere positions when overlapped).
- * Synchronises the context stream. */
+/* Algorithmic bytes one main-kernel launch moves per step: read + write of
+ * 2 x 19 populations of the storage precision per node of every replica. */
 int lbm_step_bytes(lbm_ctx *c, double *bytes);
 
 /* Adjoint form (reverse-mode derivative through Sec. 2 eq. lbe, eq.

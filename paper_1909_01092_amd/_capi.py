@@ -54,7 +54,6 @@ SIGNATURES = {
                            C.POINTER(_V)]),
     "lbm_step": (C.c_int, [_V, C.c_int32]),
     "lbm_sync": (C.c_int, [_V]),
-    "lbm_set_overlap": (C.c_int, [_V, C.c_int32]),
     "lbm_autotune": (C.c_int, [_V, C.c_int32, _V, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
     "lbm_particle_state": (C.c_int, [_V, C.c_int32, C.POINTER(LbmParticle)]),

@@ -161,11 +161,6 @@ struct lbm_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    // split steps: the main kernel's tiles far from the sphere run on stream2
-    // while the near tiles, link and particle kernels run on stream
-    hipStream_t stream2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    bool split = false;
     Layout L;
     std::vector<RepDesc> desc;
     std::vector<int32_t> tables;
@@ -215,17 +210,28 @@ int hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail((c), e_, #call);                                     \
     } while (0)
 
+// rows of one main-kernel tile of replica q for the context's block
+int tile_rows(const lbm_ctx *c, const lbm_params &q) { return std::max(1, std::min(q.ny, c->block / q.nx)); }
+
+// LDS of the main kernel for the context's block: a 3-plane ring of both
+// components' densities over the tile rows plus a one-row halo on each side
+size_t main_lds_bytes(const lbm_ctx *c) {
+    size_t elems = 0;
+    for (int r = 0; r < c->nrep; r++)
+        elems = std::max(elems, (size_t)6 * (tile_rows(c, c->p[r]) + 2) * c->p[r].nx);
+    return elems * (c->prec == LBM_FP64 ? 8 : 4);
+}
+
 // tiling of the main kernel and the workgroup tables
 void build_tiling(lbm_ctx *c) {
     const int n = c->nrep;
     c->tables.assign(3 * (n + 1), 0);
     int32_t *wg_begin = c->tables.data(), *k3_begin = wg_begin + (n + 1), *init_begin = k3_begin + (n + 1);
     int wg = 0, k3 = 0, iw = 0;
-    size_t lds_elems = 0;
     for (int r = 0; r < n; r++) {
         RepDesc &D = c->desc[r];
         const lbm_params &q = c->p[r];
-        D.ty = std::max(1, std::min(q.ny, c->block / q.nx));
+        D.ty = tile_rows(c, q);
         D.nty = (q.ny + D.ty - 1) / D.ty;
         D.cz = std::min(c->cz, q.nz);
         D.nchunk = (q.nz + D.cz - 1) / D.cz;
@@ -238,7 +244,6 @@ void build_tiling(lbm_ctx *c) {
         k3 += D.k3_count;
         init_begin[r] = iw;
         iw += (int)c->L.init_wg[r];
-        lds_elems = std::max(lds_elems, (size_t)6 * (D.ty + 2) * q.nx);
     }
     wg_begin[n] = wg;
     k3_begin[n] = k3;
@@ -246,7 +251,7 @@ void build_tiling(lbm_ctx *c) {
     c->main_grid = wg;
     c->k3_grid = k3;
     c->init_grid = iw;
-    c->lds = lds_elems * (c->prec == LBM_FP64 ? 8 : 4);
+    c->lds = main_lds_bytes(c);
 }
 
 // Longest z-chunk (a power of two up to 16) that still gives the main
@@ -257,7 +262,7 @@ int auto_zchunk(lbm_ctx *c) {
         int64_t wgs = 0;
         for (int r = 0; r < c->nrep; r++) {
             const lbm_params &q = c->p[r];
-            const int ty = std::max(1, std::min(q.ny, c->block / q.nx));
+            const int ty = tile_rows(c, q);
             wgs += (int64_t)((q.ny + ty - 1) / ty) * ((q.nz + cz - 1) / cz);
         }
         if (wgs >= want) return cz;
@@ -299,25 +304,12 @@ int enqueue_step(lbm_ctx *c, bool timed) {
             c->ev.push_back(e);
         }
     }
-    // the timed launch: the whole main kernel, or its far part when split
-    hipStream_t ts = c->split ? c->stream2 : c->stream;
-    if (c->split) {
-        HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
-    }
-    if (timed) HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], ts));
-    m.part = c->split ? 2 : 0;
-    hipError_t e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, ts);
+    if (timed) HIP_TRY(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    hipError_t e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "main kernel launch");
     if (timed) {
-        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], ts));
+        HIP_TRY(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
-    }
-    if (c->split) {
-        HIP_TRY(c, hipEventRecord(c->ev_join, c->stream2));
-        m.part = 1;
-        e = launch_main(c->prec, m, c->main_grid, c->block, c->lds, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "main kernel launch (near part)");
     }
     LinkArgs la;
     la.desc = c->d_desc();
@@ -350,41 +342,8 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     pa.finish_apart = c->k3_grid > K3_FINISH_APART ? 1 : 0;
     e = launch_particle(c->prec, pa, c->k3_grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "particle kernel launch");
-    if (c->split) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     c->cur = 1 - c->cur;
     return LBM_OK;
-}
-
-// Split steps need a sphere in some replica and a non-default caller stream.
-int set_split(lbm_ctx *c, bool on) {
-    bool any = false;
-    for (const RepDesc &D : c->desc) any = any || D.has_particle;
-    on = on && any && c->stream != nullptr;
-    if (on && !c->stream2) {
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    }
-    if (on != c->split) drop_graph(c);
-    c->split = on;
-    return LBM_OK;
-}
-
-// nodes updated by the timed main-kernel launch: all of them, or those in
-// tiles far from the spheres' boxes of the current state
-int64_t timed_nodes(lbm_ctx *c, const std::vector<RepState> &st) {
-    int64_t n = 0;
-    for (int r = 0; r < c->nrep; r++) {
-        const RepDesc &D = c->desc[r];
-        for (int ch = 0; ch < D.nchunk; ch++)
-            for (int yt = 0; yt < D.nty; yt++) {
-                const int y0 = yt * D.ty, y1 = std::min(y0 + D.ty, D.ny);
-                const int z0 = ch * D.cz, z1 = std::min(z0 + D.cz, D.nz);
-                if (c->split && tile_near_box(D, st[r].org, y0, y1, z0, z1)) continue;
-                n += (int64_t)D.nx * (y1 - y0) * (z1 - z0);
-            }
-    }
-    return n;
 }
 
 int check_rep(lbm_ctx *c, int r) {
@@ -830,10 +789,17 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk) {
         return fail(c, LBM_EINVAL, "block must be 256, 512 or 1024");
     if (zchunk < 0) return fail(c, LBM_EINVAL, "zchunk must be >= 0 (0: automatic)");
     if (block < c->maxnx) return fail(c, LBM_EINVAL, "block must hold one x-row of every replica");
+    // build the new tiling aside and commit it only when it fits, so a
+    // rejected shape leaves the context (and lbm_get_launch) as it was
+    const int old_block = c->block, old_cz = c->cz;
     c->block = block;
     c->cz = zchunk > 0 ? zchunk : auto_zchunk(c);
+    if (main_lds_bytes(c) > MAIN_LDS_MAX) {
+        c->block = old_block;
+        c->cz = old_cz;
+        return fail(c, LBM_EINVAL, "launch shape needs too much LDS");
+    }
     build_tiling(c);
-    if (c->lds > MAIN_LDS_MAX) return fail(c, LBM_EINVAL, "launch shape needs too much LDS");
     drop_graph(c);
     return upload_desc(c);
 }
@@ -851,8 +817,8 @@ LBM_API int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, in
     auto trial = [&](int blk, int cz, double &ms) -> int {
         c->block = blk;
         c->cz = cz;
+        if (main_lds_bytes(c) > MAIN_LDS_MAX) { ms = -1.0; return LBM_OK; }
         build_tiling(c);
-        if (c->lds > MAIN_LDS_MAX) { ms = -1.0; return LBM_OK; }
         drop_graph(c);
         int r = upload_desc(c);
         if (r != LBM_OK) return r;
@@ -947,18 +913,8 @@ LBM_API int lbm_timing_read(lbm_ctx *c, double *mean_ms, int64_t *count) {
 
 LBM_API int lbm_step_bytes(lbm_ctx *c, double *bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    std::vector<RepState> st(c->nrep);
-    HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_state(), sizeof(RepState) * c->nrep, hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    *bytes = 2.0 * 38.0 * (double)timed_nodes(c, st) * (double)c->es;
+    *bytes = 2.0 * 38.0 * (double)c->L.Ntot * (double)c->es;
     return LBM_OK;
-}
-
-LBM_API int lbm_set_overlap(lbm_ctx *c, int32_t enable) {
-    if (!c) return LBM_EINVAL;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return set_split(c, enable != 0);
 }
 
 LBM_API int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_t *bytes) {
@@ -1099,12 +1055,6 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     drop_graph(c);
     // teardown: errors here have no caller to go to
-    if (c->stream2) {
-        (void)hipStreamSynchronize(c->stream2);
-        (void)hipStreamDestroy(c->stream2);
-    }
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }

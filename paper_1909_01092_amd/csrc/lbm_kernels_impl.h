@@ -331,10 +331,6 @@ void k_main(MainArgs a) {
     const int yt = local % D.nty, ch = local / D.nty;
     const int y0 = yt * ty, rows = min(ty, g.ny - y0);
     const int z0 = ch * zc, z1 = min(z0 + zc, g.nz);
-    if (a.part != 0) {  // split launch: keep only this part's tiles (uniform exit)
-        const int32_t ob[3] = {stp->org[0], stp->org[1], stp->org[2]};
-        if (tile_near_box(D, ob, y0, y0 + rows, z0, z1) != (a.part == 1)) return;
-    }
     const int t = threadIdx.x;
     const int nin = nx * rows;
     const bool inner = t < nin;

@@ -64,30 +64,6 @@ struct RepState {
     uint32_t pad1[2];
 };
 
-// [a, b) against the inclusive range [lo, hi] on an axis of n nodes (the
-// range may reach outside [0, n); periodic axes compare every image)
-#if defined(__HIPCC__)
-__host__ __device__
-#endif
-inline bool span_hits(int a, int b, int lo, int hi, int n, bool wall) {
-    if (wall) return a <= hi && lo < b;
-    for (int k = -1; k <= 1; k++)
-        if (a <= hi + k * n && lo + k * n < b) return true;
-    return false;
-}
-
-// Main-kernel tile (all x, rows [y0, y1), planes [z0, z1)) that holds a node
-// within one node of the sphere's box (origin org, edge S): the link and
-// particle kernels of the step read only what such tiles write.
-#if defined(__HIPCC__)
-__host__ __device__
-#endif
-inline bool tile_near_box(const RepDesc &D, const int32_t *org, int y0, int y1, int z0, int z1) {
-    if (!D.has_particle) return false;
-    return span_hits(y0, y1, org[1] - 1, org[1] + D.S, D.ny, (D.walls & 2u) != 0) &&
-           span_hits(z0, z1, org[2] - 1, org[2] + D.S, D.nz, (D.walls & 4u) != 0);
-}
-
 constexpr uint32_t FLAG_UNSTABLE = 1u;
 // Node flag of a bounding-box node for one step: MASK_SOLID = particle node at X^n.
 constexpr uint32_t MASK_SOLID = 1u << 19;

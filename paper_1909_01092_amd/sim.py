@@ -121,11 +121,6 @@ class Simulation:
         self._check(self._lib.lbm_get_launch(self._ctx, C.byref(b), C.byref(z)))
         return b.value, z.value
 
-    def set_overlap(self, enable: bool):
-        """Run the main kernel's tiles away from the spheres on a second stream,
-        concurrently with the sphere kernels (lbm_set_overlap)."""
-        self._check(self._lib.lbm_set_overlap(self._ctx, int(bool(enable))))
-
     def set_graph(self, steps_per_graph: int):
         self._check(self._lib.lbm_set_graph(self._ctx, int(steps_per_graph)))
 

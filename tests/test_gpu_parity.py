@@ -316,34 +316,6 @@ def test_single_run_full_size_one_step_fp32(Sim):
     compare(sim, ref, 1e-7, 2e-5, what="64x64x256 one step from the GPU state")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_overlapped_steps_equal_serial_steps(Sim, prec):
-    """Main-kernel tiles away from the sphere on a second stream, concurrently
-    with the link and particle kernels, give bitwise the same run; cases with
-    cover/uncover events and with a sphere crossing periodic faces."""
-    import torch
-    cases = [workloads.channel(16, 24, kT=1e-5, radius=3.3, wet_drho=0.2, fixed_velocity=1,
-                               U0=(0.01, -0.02, 0.07), seed=5),
-             workloads.full(dict(nx=14, ny=14, nz=15, walls=0, G=1.5, kT=1e-5, init_amp=1e-3,
-                                 radius=2.5, wet_drho=0.1, U0=(0.02, -0.03, 0.05), seed=6))]
-    for p in cases:
-        a = Sim(p, prec, stream=torch.cuda.Stream())
-        b = Sim(p, prec, stream=torch.cuda.Stream())
-        b.set_overlap(False)
-        a.set_launch(256, 3)
-        b.set_launch(256, 3)
-        a.step(37)
-        b.step(37)
-        assert np.array_equal(a.populations(), b.populations())
-        pa, pb = a.particle_state(), b.particle_state()
-        for k in ("X", "U", "W", "F", "T"):
-            assert np.array_equal(pa[k], pb[k]), k
-        if prec == "fp64":
-            ref = OracleSim(p)
-            ref.step(37)
-            compare(a, ref, 1e-12, what="overlapped steps vs oracle")
-
-
 @pytest.mark.parametrize("case", ["smallest", "widest_row", "no_noise", "sphere_without_nodes"])
 def test_degenerate_and_extreme_shapes_fp64(Sim, case):
     """The smallest lattice (2 x 2 x 2, periodic), an x-row at the 256-node
