@@ -3,6 +3,9 @@
 The oracle is plain C built with gcc; it shares no source with the HIP
 library.  -ffp-contract=off keeps every product rounded on its own so the
 particle-node predicate rounds the same way as any other implementation.
+-fopenmp runs its per-node loops over z-planes in parallel; its sums are
+taken per plane in a fixed order, so the thread count does not change a bit
+of the result.
 """
 import os
 import subprocess
@@ -15,7 +18,7 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
+           "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
            "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

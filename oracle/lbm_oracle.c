@@ -27,11 +27,20 @@
  * Every loop is written in the order of the method; nothing is fused or
  * blocked.  Compile with -ffp-contract=off: the particle-node predicate must
  * round identically on every implementation.
+ *
+ * Threads.  Built with OpenMP, the per-node loops run over z-planes in
+ * parallel.  Every sum over nodes (the wetting-layer reaction, the link
+ * momentum exchange, its torque and mass flux) is taken per z-plane in
+ * (y, x, link) order and the plane sums are then added in z order, whatever
+ * the thread count, so one thread and many give bitwise the same run.
  */
 #include "lbm_oracle.h"
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -290,6 +299,7 @@ void orc_destroy(orc_sim *s) {
 /* ----------------------------------------------------- step 1: moments */
 static void moments(orc_sim *s) {
     int64_t N = s->N;
+#pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++)
         for (int l = 0; l < 2; l++) {
             double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -311,6 +321,7 @@ static void moments(orc_sim *s) {
 static void virtual_densities(orc_sim *s) {
     int64_t N = s->N;
     const orc_params *p = &s->p;
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
@@ -367,10 +378,13 @@ static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3])
     const orc_params *p = &s->p;
     double af[3], Fext[3];
     driving(s, af, Fext);
-    for (int a = 0; a < 3; a++) { Fv[a] = 0.0; Tv[a] = 0.0; }
+    /* per-plane sums of the particle-node share: [nz][6] = Fv, Tv */
+    double *pv = (double *)calloc((size_t)p->nz * 6, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
+                double *Fvz = pv + (int64_t)z * 6, *Tvz = Fvz + 3;
                 int64_t n = node_index(s, x, y, z);
                 for (int l = 0; l < 2; l++)
                     for (int a = 0; a < 3; a++) F[(l * 3 + a) * N + n] = 0.0;
@@ -398,13 +412,17 @@ static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3])
                         separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
                                    s->P.X, r);
                         cross(r, fl, t);
-                        for (int a = 0; a < 3; a++) { Fv[a] += fl[a]; Tv[a] += t[a]; }
+                        for (int a = 0; a < 3; a++) { Fvz[a] += fl[a]; Tvz[a] += t[a]; }
                     }
                 }
                 for (int l = 0; l < 2; l++)
                     for (int a = 0; a < 3; a++)
                         F[(l * 3 + a) * N + n] = sumo[l][a] + s->rho[l * N + n] * af[a];
             }
+    for (int a = 0; a < 3; a++) { Fv[a] = 0.0; Tv[a] = 0.0; }
+    for (int z = 0; z < p->nz; z++)
+        for (int a = 0; a < 3; a++) { Fv[a] += pv[z * 6 + a]; Tv[a] += pv[z * 6 + 3 + a]; }
+    free(pv);
 }
 
 void orc_forces(const orc_sim *s, double *F) {
@@ -491,6 +509,7 @@ static void collide(orc_sim *s) {
     int64_t N = s->N;
     double zero[36];
     memset(zero, 0, sizeof(zero));
+#pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         if (s->solid[n]) {
             for (int l = 0; l < 2; l++)
@@ -529,12 +548,14 @@ static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb
     const orc_params *p = &s->p;
     const orc_particle *P = &s->P;
     memset(s->fnew, 0, (size_t)(2 * Q * N) * sizeof(double));
-    for (int a = 0; a < 3; a++) { dp[a] = 0.0; dl[a] = 0.0; }
-    dMbb[0] = dMbb[1] = 0.0;
-    int64_t links = 0;
+    /* per-plane sums [nz][9] = dp, dl, dMbb, links; every destination slot
+     * has exactly one writer, so planes stream independently */
+    double *pv = (double *)calloc((size_t)p->nz * 9, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
+                double *dpz = pv + (int64_t)z * 9, *dlz = dpz + 3, *dMz = dpz + 6;
                 int64_t n = node_index(s, x, y, z);
                 if (s->solid[n]) continue;
                 for (int l = 0; l < 2; l++) FI(s->fnew, l, 0, n) = FI(s->fpost, l, 0, n);
@@ -559,17 +580,28 @@ static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb
                             double fs = FI(s->fpost, l, i, n);
                             FI(s->fnew, l, io, n) = fs - corr;
                             for (int a = 0; a < 3; a++) lp[a] += (2.0 * fs - corr) * CV[i][a];
-                            dMbb[l] -= corr;
+                            dMz[l] -= corr;
                         }
                         double t[3];
                         cross(r, lp, t);
-                        for (int a = 0; a < 3; a++) { dp[a] += lp[a]; dl[a] += t[a]; }
-                        links++;
+                        for (int a = 0; a < 3; a++) { dpz[a] += lp[a]; dlz[a] += t[a]; }
+                        dMz[2] += 1.0;
                         continue;
                     }
                     for (int l = 0; l < 2; l++) FI(s->fnew, l, i, m) = FI(s->fpost, l, i, n);
                 }
             }
+    for (int a = 0; a < 3; a++) { dp[a] = 0.0; dl[a] = 0.0; }
+    dMbb[0] = dMbb[1] = 0.0;
+    int64_t links = 0;
+    for (int z = 0; z < p->nz; z++) {
+        const double *v = pv + (int64_t)z * 9;
+        for (int a = 0; a < 3; a++) { dp[a] += v[a]; dl[a] += v[3 + a]; }
+        dMbb[0] += v[6];
+        dMbb[1] += v[7];
+        links += (int64_t)v[8];
+    }
+    free(pv);
     return links;
 }
 
@@ -620,6 +652,7 @@ static void one_step(orc_sim *s) {
 
     /* 9: cover / uncover against the particle nodes at X^{n+1} */
     double dMcov[2] = {0, 0}, dMunc[2] = {0, 0};
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
@@ -683,6 +716,7 @@ static void one_step(orc_sim *s) {
                 P->n_uncovered++;
             }
     /* covered nodes drop their populations */
+#pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++)
         if (s->solid_new[n])
             for (int l = 0; l < 2; l++)
@@ -692,6 +726,7 @@ static void one_step(orc_sim *s) {
     double nf = 0.0;
     for (int64_t n = 0; n < N; n++) nf += s->solid_new[n] ? 0.0 : 1.0;
     for (int l = 0; l < 2; l++) P->delta[l] = -(dMbb[l] + dMcov[l] + dMunc[l]) / nf;
+#pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         if (s->solid_new[n]) continue;
         for (int l = 0; l < 2; l++)
@@ -702,6 +737,16 @@ static void one_step(orc_sim *s) {
     double *t = s->f; s->f = s->fnew; s->fnew = t;
     unsigned char *u8 = s->solid; s->solid = s->solid_new; s->solid_new = u8;
     P->step++;
+}
+
+int orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 void orc_step(orc_sim *s, int32_t nsteps) {

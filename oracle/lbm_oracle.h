@@ -56,6 +56,10 @@ typedef struct orc_sim orc_sim;
 orc_sim *orc_create(const orc_params *p);
 void orc_destroy(orc_sim *s);
 void orc_step(orc_sim *s, int32_t nsteps);
+/* Threads of the per-node loops (n > 0 sets them; n <= 0 only queries);
+ * returns the count in effect (1 without OpenMP).  Results do not depend
+ * on it. */
+int orc_set_threads(int32_t n);
 /* f = [2][19][nz][ny][nx] populations f_{l i}(x, n) after streaming and mass
  * correction (solid nodes hold zero).                                        */
 void orc_get_populations(const orc_sim *s, double *f);

@@ -69,7 +69,15 @@ def lib():
         _lib.orc_forces.argtypes = [C.c_void_p, d]
         _lib.orc_adjoint.restype = C.c_int
         _lib.orc_adjoint.argtypes = [C.c_void_p, C.c_int32, d, d]
+        _lib.orc_set_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int32]
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's per-node loops (n <= 0: leave as is); returns
+    the count in effect.  Results are bitwise independent of it."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.0,
