@@ -213,12 +213,12 @@ int hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
 // rows of one main-kernel tile of replica q for the context's block
 int tile_rows(const lbm_ctx *c, const lbm_params &q) { return std::max(1, std::min(q.ny, c->block / q.nx)); }
 
-// LDS of the main kernel for the context's block: a 3-plane ring of both
+// LDS of the main kernel for the context's block: a 4-plane ring of both
 // components' densities over the tile rows plus a one-row halo on each side
 size_t main_lds_bytes(const lbm_ctx *c) {
     size_t elems = 0;
     for (int r = 0; r < c->nrep; r++)
-        elems = std::max(elems, (size_t)6 * (tile_rows(c, c->p[r]) + 2) * c->p[r].nx);
+        elems = std::max(elems, (size_t)8 * (tile_rows(c, c->p[r]) + 2) * c->p[r].nx);
     return elems * (c->prec == LBM_FP64 ? 8 : 4);
 }
 

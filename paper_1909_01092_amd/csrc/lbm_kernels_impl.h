@@ -301,7 +301,7 @@ __device__ __forceinline__ int xcd_logical(int b, int G) {
 // ================================================================ k_main
 // Workgroup = ty full x-rows of one replica, marching over cz z-planes.
 // Density deviations of the tile plus a one-node halo (rows y0-1 and
-// y0+rows, planes z-1 and z+1) sit in a 3-plane LDS ring; halo densities are
+// y0+rows, planes z-1 and z+1) sit in a 4-plane LDS ring; halo densities are
 // recomputed from pulled populations, so no density field goes through HBM.
 // The density and momenta of the next plane stay in registers while the
 // current plane collides.  The sphere enters only through the solid flags
@@ -358,8 +358,10 @@ void k_main(MainArgs a) {
     uint32_t k0 = key0, k1 = key1;
     PullCtx<S, T> pcl = pc;
 
+    // four plane slots: the fill of the next plane never lands on a slot the
+    // collision of the current plane still reads, so one barrier per plane
     auto L = [&](int zp, int l, int row, int xx) -> T & {
-        const int slot = ((zp % 3) + 3) % 3;
+        const int slot = zp & 3;
         return lds[(slot * 2 + l) * pr + (row + 1) * nx + xx];
     };
 
@@ -527,7 +529,6 @@ void k_main(MainArgs a) {
                 }
             }
         }
-        __syncthreads();
     }
 }
 

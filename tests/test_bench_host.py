@@ -74,7 +74,25 @@ def test_cpu_baseline_leg():
     reps, prec, _ = bench.workload("parity")
     cb = bench.cpu_baseline(reps, budget_s=0.5)
     assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
-    assert cb["unit"] == "MLUPS" and cb["kind"] == "oracle" and cb["cores"] == 1
+    assert cb["unit"] == "MLUPS" and cb["kind"] == "oracle" and cb["cores"] == bench.oracle_threads()
     assert cb["value"] > 0.0
     p = reps[0]
     assert f"{p['nx']}x{p['ny']}x{p['nz']}" in cb["sample"] and "FP64" in cb["sample"]
+    assert "one replica" in cb["sample"]
+
+
+def test_cpu_baseline_slab_of_a_large_replica():
+    """A replica above max_nodes is sampled as a slab of slab_nz planes with
+    the same cross-section and sphere."""
+    reps, _, _ = bench.workload("parity")
+    cb = bench.cpu_baseline(reps, budget_s=0.2, max_nodes=1000, slab_nz=16)
+    assert "24x24x16" in cb["sample"] and "slab" in cb["sample"] and cb["value"] > 0.0
+
+
+def test_timing_interval():
+    assert bench.timing_every(20) == 1 and bench.timing_every(99) == 1 and bench.timing_every(100) == 10
+
+
+def test_valu_peak():
+    # 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles each, 2.4 GHz
+    assert abs(bench.VALU_PEAK_GINSTR - 614.4) < 1e-9

@@ -56,8 +56,8 @@ def test_friction_channel_parity(Sim):
 def test_confinement_friction_trend(Sim):
     import torch
     sys.path.insert(0, ROOT)
-    import bench
-    out = bench.friction_study(torch, steps=12000)
+    from paper_1909_01092_amd import studies
+    out = studies.friction_study(torch, steps=12000)
     for r in out["rows"]:
         print(f"  d/L {r['d_over_L']:.3f}  U {r['U']:.4e}  c_m {r['c_m']:.3f}  Re {r['Re']:.1e}  "
               f"drift {r['drift']:.1e}", flush=True)
@@ -80,9 +80,9 @@ def test_friction_almost_independent_of_wettability(Sim):
     and the neutral sphere's c_m is the miscible mixture's."""
     import torch
     sys.path.insert(0, ROOT)
-    import bench
-    wet = bench.friction_study(torch, steps=30000, tail=10000, wettability=True)
-    ref = {round(r["R"], 2): r["c_m"] for r in bench.friction_study(torch, steps=12000)["rows"]}
+    from paper_1909_01092_amd import studies
+    wet = studies.friction_study(torch, steps=30000, tail=10000, wettability=True)
+    ref = {round(r["R"], 2): r["c_m"] for r in studies.friction_study(torch, steps=12000)["rows"]}
     by = {}
     for r in wet["rows"]:
         print(f"  {r['wettability']:11s} d/L {r['d_over_L']:.3f}  c_m {r['c_m']:.3f}  drift {r['drift']:.1e}  "

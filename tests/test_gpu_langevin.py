@@ -1,5 +1,5 @@
 """Statistics of the particle velocity over an ensemble of noise replicas,
-against the Langevin picture the paper verifies (Sec. 3, Langevin section):
+against the Langevin picture the paper verifies (Sec. 4, eq. MEANVARIANCE):
 in the steady state Var(U) = kT / m_p whatever kT, sphere size and driving
 (Delta U = sqrt(6 kT / (pi rho_p L^3)) (d/L)^(-3/2)), the standardized
 velocity is Gaussian, and the mean settling velocity does not depend on kT.  These run the HIP path only; the expected values are the

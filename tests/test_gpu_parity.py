@@ -95,7 +95,7 @@ def test_sphere_fp64_parity_small_channel(Sim):
     for n in (1, 9, 40, 150):
         sim.step(n)
         ref.step(n)
-        compare(sim, ref, 1e-12, what=f"sphere after +{n}")
+        compare(sim, ref, 1e-12, 1e-12, what=f"sphere after +{n}")
     compare_particle(sim, ref, 1e-9, what="sphere 200 steps")
     pg = sim.particle_state()
     print(f"events: covered {pg['n_covered']} uncovered {pg['n_uncovered']}", flush=True)
@@ -141,18 +141,74 @@ def test_fp32_parity_small_channel(Sim):
 def test_fp32_parity_single_run_slice(Sim):
     """A 64 x 64 x 64 slice of the single-run channel (R = 8, kT = 1e-5,
     g = 1e-4) in the benchmark's launch shape (full 64-node rows, 256 x 4):
-    60 FP32 steps against the oracle."""
+    200 FP32 steps against the oracle."""
     p = dict(workloads.SINGLE_RUN, nz=64, X0=None)
     p = workloads.full(p)
     sim, ref = Sim(p, "fp32"), OracleSim(p)
     sim.set_launch(256, 4)
-    sim.step(60)
-    ref.step(60)
-    compare(sim, ref, 1e-6, 1e-5, what="64x64x64 slice, fp32 60 steps")
+    sim.step(200)
+    ref.step(200)
+    compare(sim, ref, 1e-6, 1e-5, what="64x64x64 slice, fp32 200 steps")
     pg, po = sim.particle_state(), ref.particle()
     errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
     print(f"slice particle U rel err {errU:.3e}", flush=True)
     assert errU < 1e-5
+
+
+# distinct relaxation times per mode group (shear, bulk, momentum, ghost),
+# the brute-force pin's set: the general MRT collision of Sec. 2
+MRT_TAUS = dict(tau_shear=0.8, tau_bulk=1.1, tau_mom=0.9, tau_ghost=1.3)
+
+
+@pytest.mark.parametrize("prec,tol,tol_dev", [("fp64", 1e-12, 1e-12), ("fp32", 1e-6, 1e-5)])
+def test_general_mrt_rates_with_events(Sim, prec, tol, tol_dev):
+    """The MRT collision with a distinct relaxation rate per mode group (Sec. 2,
+    MRT paragraph) on a walled channel whose sphere is driven through cover /
+    uncover events, with wetting, noise and a body force: 200 steps against
+    the oracle, FP64 at 1e-12 and FP32 deviations at 1e-5."""
+    p = workloads.channel(16, 24, kT=1e-5, radius=3.3, wet_drho=0.2, fixed_velocity=1,
+                          U0=(0.01, -0.02, 0.07), W0=(0.0, 0.01, 0.0), g=(0.0, 0.0, 1e-4), seed=5,
+                          **MRT_TAUS)
+    sim, ref = Sim(p, prec), OracleSim(p)
+    sim.set_launch(256, 5)
+    for n in (7, 193):
+        sim.step(n)
+        ref.step(n)
+        compare(sim, ref, tol, tol_dev, what=f"MRT rates {prec} +{n}")
+    pg, po = compare_particle(sim, ref, 1e-9 if prec == "fp64" else 1e-5, what=f"MRT rates {prec}")
+    assert po["n_covered"] > 10 and po["n_uncovered"] > 10
+
+
+@pytest.mark.parametrize("prec,tol_dev,tol_u", [("fp64", 1e-12, 1e-10), ("fp32", 1e-5, 1e-5)])
+def test_general_mrt_rates_free_sphere_parity_channel(Sim, prec, tol_dev, tol_u):
+    """The 24 x 24 x 48 parity channel with a free sphere and distinct
+    relaxation rates per mode group, 200 steps."""
+    p = dict(workloads.PARITY_SMALL, **MRT_TAUS)
+    sim, ref = Sim(p, prec), OracleSim(p)
+    sim.step(200)
+    ref.step(200)
+    compare(sim, ref, 1e-6 if prec == "fp32" else 1e-12, tol_dev, what=f"MRT rates parity channel {prec}")
+    pg, po = sim.particle_state(), ref.particle()
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    print(f"MRT rates {prec}: particle U rel err {errU:.3e}", flush=True)
+    assert errU < tol_u
+
+
+def test_rejected_launch_shape_leaves_the_context_unchanged(Sim):
+    """A shape whose LDS does not fit (FP64, 200-node rows, 1024 threads) is
+    rejected with LBM_EINVAL, and the context keeps its previous shape:
+    lbm_get_launch reports it and the following steps match the oracle."""
+    from paper_1909_01092_amd._capi import LbmError
+    p = workloads.full(dict(nx=200, ny=6, nz=9, walls=3, G=1.5, kT=1e-5, init_amp=1e-3,
+                            g=(0.0, 0.0, 1e-5), force_mode=1, seed=21))
+    sim, ref = Sim(p, "fp64"), OracleSim(p)
+    sim.set_launch(256, 4)
+    with pytest.raises(LbmError):
+        sim.set_launch(1024, 2)
+    assert sim.get_launch() == (256, 4)
+    sim.step(12)
+    ref.step(12)
+    compare(sim, ref, 1e-12, 1e-12, what="after a rejected launch shape")
 
 
 def test_fp16_error_reported(Sim):
@@ -264,6 +320,33 @@ def test_many_replicas_finish_apart_fp64(Sim):
         if k != 20:
             pg, po = compare_particle(sim, ref, 1e-10, rep=k, what=f"replica {k} of 40")
             assert po["n_covered"] > 0 and po["n_uncovered"] > 0
+
+
+@pytest.mark.timeout(900)
+def test_large_full_size_one_step_fp16(Sim):
+    """192 x 192 x 1024, R = 16, kT = 1e-4, FP16 relative-deviation storage in
+    the large workload's launch shape (1024 threads, z-chunk 32): the GPU
+    state after 20 steps is handed to the oracle, which takes one step; the
+    GPU's next step must agree to FP16's storage rounding.  Each stored
+    relative deviation is rounded to 11 bits (error <= 2^-12 of itself), so
+    the deviations agree to 2^-12 = 2.4e-4 normwise plus FP32 arithmetic;
+    asserted at 3e-4 (deviations) and 2e-6 (full populations)."""
+    p = workloads.LARGE
+    sim = Sim(p, "fp16")
+    sim.set_launch(1024, 32)
+    sim.step(20)
+    f0, p0 = sim.populations(), sim.particle_state()
+    ref = OracleSim(p)
+    ref.set_populations(f0)
+    del f0
+    ref.set_particle({k: p0[k] for k in ("X", "U", "W", "Pev", "Lev", "step", "n_fluid")})
+    sim.step(1)
+    ref.step(1)
+    compare(sim, ref, 2e-6, 3e-4, what="192x192x1024 FP16 one step from the GPU state")
+    pg, po = sim.particle_state(), ref.particle()
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    print(f"192x192x1024 one step: particle U rel err {errU:.3e}", flush=True)
+    assert errU < 1e-3
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -447,8 +530,8 @@ def test_fp16_storage_error_on_the_large_channel(Sim):
     import sys
     import torch
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    import bench
-    out = bench.fp16_error(torch, 2000)
+    from paper_1909_01092_amd import studies
+    out = studies.fp16_error(torch, 2000)
     print({k: out[k] for k in ("uz_profile_rel_l2", "mean_Uz_rel", "var_Uz_rel", "unstable")}, flush=True)
     assert not out["unstable"]
     assert out["uz_profile_rel_l2"] < 2e-3

@@ -65,8 +65,8 @@ def test_interface_start_parity(Sim):
 def test_contact_angle_sweep(Sim):
     import torch
     sys.path.insert(0, ROOT)
-    import bench
-    out = bench.wetting_study(torch, steps=30000)
+    from paper_1909_01092_amd import studies
+    out = studies.wetting_study(torch, steps=30000)
     rows = out["rows"]
     for r in rows:
         print(f"  drho {r['drho']:+.3f}  z_i - Z {r['zi_minus_Z']:+.3f} (+-{r['spread']:.3f})  "
@@ -92,8 +92,8 @@ def test_contact_angle_sweep(Sim):
 def test_sphere_trapped_at_interface_under_force(Sim):
     import torch
     sys.path.insert(0, ROOT)
-    import bench
-    out = bench.interface_study(torch, steps=30000)
+    from paper_1909_01092_amd import studies
+    out = studies.interface_study(torch, steps=30000)
     R = workloads.WETTING_R
     by = {}
     for r in out["rows"]:
