@@ -111,11 +111,13 @@ def _slab_golden():
     return g, json.loads(str(g["meta"]))
 
 
-# per-observable bounds on the large-channel slab: FP32 at the benchmark spec's 1e-5;
-# FP16 from its 2^-12 storage rounding, as in the series test above (the
-# variance of U_z over the second half is dominated by its deterministic
-# rise, so its error follows that of U_z)
-SLAB_BOUNDS = {"fp32": dict(profile=1e-5, Uz=1e-5, mean=1e-5, var=1e-5, mass=1e-9),
+# per-observable bounds on the large-channel slab: FP32 at the benchmark spec's 1e-5,
+# the masses at 1e-6 (a sum of populations each rounded to FP32, unit
+# roundoff 6e-8, with the mass correction holding the total); FP16 from its
+# 2^-12 storage rounding, as in the series test above (the variance of U_z
+# over the second half is dominated by its deterministic rise, so its error
+# follows that of U_z)
+SLAB_BOUNDS = {"fp32": dict(profile=1e-5, Uz=1e-5, mean=1e-5, var=1e-5, mass=1e-6),
                "fp16": dict(profile=2e-2, Uz=2e-3, mean=2e-3, var=5e-3, mass=1e-5)}
 
 
