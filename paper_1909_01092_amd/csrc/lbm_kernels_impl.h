@@ -412,7 +412,9 @@ void k_main(MainArgs a) {
     };
 
     const int xm = mirror1(x - 1, nx, g.wx), xp = mirror1(x + 1, nx, g.wx);
-    const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == g.ny - 1;
+    // x / y faces of this lane's node as bits (x low, x high, y low, y high)
+    uint32_t xyface = (x == 0 ? 1u : 0u) | (x == nx - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
+                      (y == g.ny - 1 ? 8u : 0u);
 
     // Plane zp is filled while the plane filled before it collides.  Odd
     // z-chunks march downwards, so two neighbouring chunks read the halo
@@ -425,6 +427,9 @@ void k_main(MainArgs a) {
         // keep uniform values derived from these roots inside the loop (scalar
         // recomputation is cheaper than spilling hoisted copies)
         asm volatile("" : "+s"(k0), "+s"(k1), "+s"(pcl.NP), "+s"(pcl.PX), "+s"(pcl.PXY));
+        // face tests are redone per plane from these bits instead of being
+        // hoisted as lane masks that would crowd the scalar registers
+        asm volatile("" : "+v"(xyface));
         const int zp = zfirst + dir * k;
         const NodeM<T, TAU1> cur = nxt;
         const bool cur_fluid = nxt_fluid;
@@ -472,6 +477,8 @@ void k_main(MainArgs a) {
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
             const bool zlo = z == 0, zhi = z == g.nz - 1;
+            const bool yzface = (xyface & 12u) != 0u || zlo || zhi;
+            const bool xonly = !yzface && (xyface & 3u) != 0u;
             constexpr int kCompUnroll = main_unroll<S, T, TAU1> ? 2 : 1;
 #pragma unroll kCompUnroll
             for (int l = 0; l < 2; l++) {
@@ -507,24 +514,48 @@ void k_main(MainArgs a) {
                     const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
                     S *col = dl_base + i * pcl.NP;
                     st_dev<S, T>(&at(col, own4), out[i], inv);
-                    if (i == 0) continue;
-                    // a link that leaves the box also writes its value where the
-                    // receiver pulls it from: the wall ghost x + c_i, slot opp(i)
-                    // (half-way bounce-back), or the periodic image of x, slot i
-                    const bool ex = cx(i) > 0 ? xhi : (cx(i) < 0 ? xlo : false);
-                    const bool ey = cy(i) > 0 ? yhi : (cy(i) < 0 ? ylo : false);
-                    const bool ez = cz(i) > 0 ? zhi : (cz(i) < 0 ? zlo : false);
-                    if (ex || ey || ez) {
-                        // element index from the component base: slot * NP + target,
-                        // never negative (x + c_i lies in the ghost layer, the
-                        // periodic image x - n c_i inside the box)
-                        const bool bounce = (ex && g.wx) || (ey && g.wy) || (ez && g.wz);
-                        const int32_t so = bounce ? opp(i) * pcl.NP + pcl.PX * cy(i) + pcl.PXY * cz(i) + cx(i)
-                                                  : i * pcl.NP + (ex ? -cx(i) * nx : 0) +
-                                                        (ey ? -cy(i) * g.ny * g.PX : 0) +
-                                                        (ez ? -cz(i) * g.nz * g.PX * g.PY : 0);
-                        const uint32_t e = (uint32_t)((int32_t)own + so);
-                        st_dev<S, T>(&at(dl_base, e * (uint32_t)sizeof(S)), out[i], inv);
+                }
+                // A link that leaves the box also writes its value where the
+                // receiver pulls it from: the wall ghost x + c_i, slot opp(i)
+                // (half-way bounce-back), or the periodic image of x, slot i.
+                // Only nodes on a face do.  Nodes on an x-face alone (the
+                // common case: two per row) write the links with c_x pointing
+                // out, at offsets uniform over the wave; nodes on a y- or
+                // z-face take the general form.
+                if (xonly) {
+                    const bool hi = xyface & 2u;
+#pragma unroll
+                    for (int i = 1; i < Q; i++) {
+                        if (cx(i) == 0) continue;
+                        const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
+                        const int32_t so = g.wx ? opp(i) * pcl.NP + pcl.PX * cy(i) + pcl.PXY * cz(i) + cx(i)
+                                                : i * pcl.NP - cx(i) * nx;
+                        if ((cx(i) > 0) == hi) {
+                            const uint32_t e = (uint32_t)((int32_t)own + so);
+                            st_dev<S, T>(&at(dl_base, e * (uint32_t)sizeof(S)), out[i], inv);
+                        }
+                    }
+                }
+                if (yzface) {
+                    const bool xlo = xyface & 1u, xhi = xyface & 2u, ylo = xyface & 4u, yhi = xyface & 8u;
+#pragma unroll
+                    for (int i = 1; i < Q; i++) {
+                        const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
+                        const bool ex = cx(i) > 0 ? xhi : (cx(i) < 0 ? xlo : false);
+                        const bool ey = cy(i) > 0 ? yhi : (cy(i) < 0 ? ylo : false);
+                        const bool ez = cz(i) > 0 ? zhi : (cz(i) < 0 ? zlo : false);
+                        if (ex || ey || ez) {
+                            // element index from the component base: slot * NP + target,
+                            // never negative (x + c_i lies in the ghost layer, the
+                            // periodic image x - n c_i inside the box)
+                            const bool bounce = (ex && g.wx) || (ey && g.wy) || (ez && g.wz);
+                            const int32_t so = bounce ? opp(i) * pcl.NP + pcl.PX * cy(i) + pcl.PXY * cz(i) + cx(i)
+                                                      : i * pcl.NP + (ex ? -cx(i) * nx : 0) +
+                                                            (ey ? -cy(i) * g.ny * g.PX : 0) +
+                                                            (ez ? -cz(i) * g.nz * g.PX * g.PY : 0);
+                            const uint32_t e = (uint32_t)((int32_t)own + so);
+                            st_dev<S, T>(&at(dl_base, e * (uint32_t)sizeof(S)), out[i], inv);
+                        }
                     }
                 }
             }

@@ -35,14 +35,23 @@ __host__ __device__ __forceinline__ constexpr double wgt(int i) {
 
 // ------------------------------------------------------------ Philox4x32-10
 // Salmon et al. (SC'11): 10 rounds of two 32x32->64 products, Weyl key bumps.
+// three-way xor: one v_bitop3_b32 (truth table 0x96) on gfx950
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 __host__ __device__ inline void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
                                               uint32_t &c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -63,29 +72,29 @@ __host__ __device__ inline void box_muller(uint32_t w1, uint32_t w2, double &z0,
     z1 = r * sin(a);
 }
 
-// FP32 form.  ln u1 keeps full relative accuracy for u1 near 1 by working
-// with v = 1 - u1 (exact from the complemented word) and the log1p identity
-// ln(1 - v) = ln(t) (-v)/(t - 1), t = fl(1 - v).  Angles are taken in
-// revolutions, which is what the hardware sine / cosine consume.
+// FP32 form.  ln u1 keeps full relative accuracy for u1 near 1: with
+// v = 1 - u1 (exact from the complemented word) and t = fl(1 - v), the
+// rounding error e = (1 - t) - v is exact (Sterbenz), and
+// ln(1 - v) = ln(t + e) = ln t + e / t + O(e^2) = ln t + e (1 + O(v)),
+// so ln u1 = ln t + e to a few FP32 ulps; for u1 < 1/2 e = 0.  Angles are
+// taken in revolutions, which is what the hardware sine / cosine consume.
 __host__ __device__ inline void box_muller(uint32_t w1, uint32_t w2, float &z0, float &z1) {
     const bool big = w1 >= 0x80000000u;
-    const float v = ((float)(big ? ~w1 : w1) + 0.5f) * 0x1p-32f;
+    const float v = __builtin_fmaf((float)(big ? ~w1 : w1), 0x1p-32f, 0x1p-33f);
     const float t = big ? 1.0f - v : v;
+    const float e = big ? (1.0f - t) - v : 0.0f;
 #if defined(__HIP_DEVICE_COMPILE__)
-    const float L = __builtin_amdgcn_logf(t) * 0.69314718055994531f;
-    const float ratio = -v * __builtin_amdgcn_rcpf(t - 1.0f);
+    const float m2lnu = __builtin_fmaf(__builtin_amdgcn_logf(t), -1.3862943611198906f, -2.0f * e);
 #else
-    const float L = logf(t);
-    const float ratio = -v / (t - 1.0f);
+    const float m2lnu = -2.0f * (logf(t) + e);
 #endif
-    const float lnu = big ? ((t == 1.0f) ? -v : L * ratio) : L;
-    const float u2 = ((float)w2 + 0.5f) * 0x1p-32f;
+    const float u2 = __builtin_fmaf((float)w2, 0x1p-32f, 0x1p-33f);
 #if defined(__HIP_DEVICE_COMPILE__)
-    const float r = __builtin_amdgcn_sqrtf(-2.0f * lnu);
+    const float r = __builtin_amdgcn_sqrtf(m2lnu);
     const float c = __builtin_amdgcn_cosf(u2);
     const float s = __builtin_amdgcn_sinf(u2);
 #else
-    const float r = sqrtf(-2.0f * lnu);
+    const float r = sqrtf(m2lnu);
     const float c = (float)cos(6.283185307179586 * u2);
     const float s = (float)sin(6.283185307179586 * u2);
 #endif
