@@ -549,6 +549,15 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
             }
         }
     }
+    for (int r = 0; r < n_replicas; r++) {
+        RepDesc &D = c->desc[r];
+        D.cf32 = make_coef<float>(D.rho0[0], D.rho0[1], D.tau[0], D.tau[1], D.tau[2], D.tau[3], D.kT,
+                                  D.noise_diffusive);
+        D.cf64 = make_coef<double>(D.rho0[0], D.rho0[1], D.tau[0], D.tau[1], D.tau[2], D.tau[3], D.kT,
+                                   D.noise_diffusive);
+        D.G32 = (float)D.G;
+        for (int a = 0; a < 3; a++) D.af32[a] = (float)D.af[a];
+    }
     rc = upload_desc(c);
     if (rc != LBM_OK) { g_init_error = c->err; delete c; return rc; }
     c->cur = 0;

@@ -34,8 +34,7 @@ namespace lbm {
 
 template <typename T>
 __device__ __forceinline__ Coef<T> make_coef_dev(const RepDesc &D) {
-    return make_coef<T>(D.rho0[0], D.rho0[1], D.tau[0], D.tau[1], D.tau[2], D.tau[3], D.kT,
-                        D.noise_diffusive);
+    return coef_of<T>(D);
 }
 
 // ------------------------------------------------------------ storage forms
@@ -351,8 +350,9 @@ void k_main(MainArgs a) {
     S *__restrict__ dst = reinterpret_cast<S *>(a.dst) + D.pop_off;
     const uint32_t NP = g.NP;
     const double rho0d[2] = {D.rho0[0], D.rho0[1]};
-    const T G = T(D.G);
-    const T af[3] = {T(D.af[0]), T(D.af[1]), T(D.af[2])};
+    const T G = sizeof(T) == 4 ? T(D.G32) : T(D.G);
+    const T af[3] = {sizeof(T) == 4 ? T(D.af32[0]) : T(D.af[0]), sizeof(T) == 4 ? T(D.af32[1]) : T(D.af[1]),
+                     sizeof(T) == 4 ? T(D.af32[2]) : T(D.af[2])};
     const uint32_t key0 = D.key0, key1 = D.key1;
     const Coef<T> cf = make_coef_dev<T>(D);
     uint32_t k0 = key0, k1 = key1;

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #endif
 
+#include "lbm_math.h"
+
 namespace lbm {
 
 struct RepDesc {
@@ -46,7 +48,16 @@ struct RepDesc {
     int32_t noise_diffusive, fixed_velocity;
     int32_t init_split;      // first plane of the swapped initial phase (0: none)
     int32_t pad_split;
+    // collision coefficients and forcing in both arithmetic precisions, made
+    // once on the host (kernels load them as wave-uniform values)
+    Coef<float> cf32;
+    Coef<double> cf64;
+    float G32, af32[3];
 };
+
+template <typename T> __host__ __device__ __forceinline__ const Coef<T> &coef_of(const RepDesc &D);
+template <> __host__ __device__ __forceinline__ const Coef<float> &coef_of<float>(const RepDesc &D) { return D.cf32; }
+template <> __host__ __device__ __forceinline__ const Coef<double> &coef_of<double>(const RepDesc &D) { return D.cf64; }
 
 struct RepState {
     double X[3], Xp[3];      // X^n and X^{n-1}
