@@ -338,6 +338,7 @@ void k_main(MainArgs a) {
     const int pr = (ty + 2) * nx;  // LDS elements per plane and component
 
     const bool hp = D.has_particle;
+    const bool ghost_fill = D.ghost_fill;
     const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
     const T dl[2] = {T(stp->delta[0]), T(stp->delta[1])};
     const double dld[2] = {stp->delta[0], stp->delta[1]};
@@ -514,6 +515,23 @@ void k_main(MainArgs a) {
                     const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
                     S *col = dl_base + i * pcl.NP;
                     st_dev<S, T>(&at(col, own4), out[i], inv);
+                }
+                // Narrow rows: the two x-ghost elements between consecutive rows
+                // share a cache line with both rows' ends, and a line left partly
+                // unwritten costs a read-modify-write in HBM.  The x-face nodes
+                // then also fill the ghost slots no node ever pulls from (c_x <= 0
+                // beside x = 0, c_x >= 0 beside x = nx - 1), so every such line is
+                // written whole.
+                if (ghost_fill && (xyface & 3u) != 0u) {
+                    const bool hi = xyface & 2u;
+#pragma unroll
+                    for (int i = 0; i < Q; i++) {
+                        const T inv = Rel<S>::value ? T(1) / (T(wgt(i)) * sc) : T(1);
+                        if (hi ? cx(i) >= 0 : cx(i) <= 0) {
+                            const uint32_t e = (uint32_t)((int32_t)own + (hi ? 1 : -1) + i * pcl.NP);
+                            st_dev<S, T>(&at(dl_base, e * (uint32_t)sizeof(S)), out[i], inv);
+                        }
+                    }
                 }
                 // A link that leaves the box also writes its value where the
                 // receiver pulls it from: the wall ghost x + c_i, slot opp(i)

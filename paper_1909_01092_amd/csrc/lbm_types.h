@@ -47,7 +47,7 @@ struct RepDesc {
     uint32_t key0, key1;
     int32_t noise_diffusive, fixed_velocity;
     int32_t init_split;      // first plane of the swapped initial phase (0: none)
-    int32_t pad_split;
+    int32_t ghost_fill;      // main kernel also writes the never-pulled x-ghost slots
     // collision coefficients and forcing in both arithmetic precisions, made
     // once on the host (kernels load them as wave-uniform values)
     Coef<float> cf32;
