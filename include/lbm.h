@@ -144,6 +144,22 @@ int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision, void *d
 /* Advance every replica by nsteps (asynchronous). */
 int lbm_step(lbm_ctx *c, int32_t nsteps);
 
+/* lbm_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same steps, bitwise, with the per-step scratch of the step kernels
+ * (link and event partial sums, the sphere box's post-streaming moments and
+ * step densities) taken from a static device array of the library
+ * (16 MiB; each GPU the library runs on holds its own until the process
+ * ends) instead of the context workspace.  Makes no allocation and no
+ * library call that allocates.  Plain launches only (lbm_set_graph is not
+ * used).  Every call on one GPU shares that GPU's array: calls whose steps
+ * overlap on one GPU (two contexts on two streams) race and must be
+ * serialised by the caller.  LBM_EINVAL for nsteps < 0 or a context whose
+ * step scratch exceeds 16 MiB (56 bytes per sphere-box node, summed over
+ * the replicas, plus 384 bytes per 64 box nodes, each rounded up to 256);
+ * LBM_EDEVICE if the array's address cannot be obtained. */
+int lbm_step_noalloc(lbm_ctx *c, int32_t nsteps);
+
 /* Blocks until the context's stream has drained. */
 int lbm_sync(lbm_ctx *c);
 

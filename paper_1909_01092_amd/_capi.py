@@ -53,6 +53,7 @@ SIGNATURES = {
     "lbm_init": (C.c_int, [C.POINTER(LbmParams), C.c_int32, C.c_int32, _V, C.c_size_t, _V,
                            C.POINTER(_V)]),
     "lbm_step": (C.c_int, [_V, C.c_int32]),
+    "lbm_step_noalloc": (C.c_int, [_V, C.c_int32]),
     "lbm_sync": (C.c_int, [_V]),
     "lbm_autotune": (C.c_int, [_V, C.c_int32, _V, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),

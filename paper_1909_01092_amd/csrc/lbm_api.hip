@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,15 @@ using namespace lbm;
 namespace {
 
 thread_local std::string g_init_error;
+
+// Static per-step scratch for lbm_step_noalloc.  In host code `scratch`
+// names a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(16) << 20;
+constexpr int MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[MAX_DEVICES] = {};
 
 constexpr size_t ALIGN = 256;
 constexpr int MAIN_BLOCK_MIN = 256;
@@ -161,6 +171,7 @@ struct lbm_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
+    int device = 0;           // device current at lbm_init (the stream's)
     Layout L;
     std::vector<RepDesc> desc;
     std::vector<int32_t> tables;
@@ -285,7 +296,18 @@ void drop_graph(lbm_ctx *c) {
     c->graph_parity = -1;
 }
 
-int enqueue_step(lbm_ctx *c, bool timed) {
+// Per-step scratch of the step kernels: link and event partials, the box
+// nodes' post-streaming moments and step densities.  Written and consumed
+// within one step; nothing in it carries over.
+struct StepScratch {
+    double *part1, *part3, *raw, *rho_n;
+};
+
+StepScratch workspace_scratch(lbm_ctx *c) {
+    return {c->d_part1(), c->d_part3(), c->d_raw(), c->d_rho_n()};
+}
+
+int enqueue_step(lbm_ctx *c, bool timed, const StepScratch &sc) {
     MainArgs m;
     m.desc = c->d_desc();
     m.state = c->d_state();
@@ -295,7 +317,7 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     m.dst = c->d_pop(1 - c->cur);
     m.pmask = c->d_pmask();
     m.vrho = c->d_vrho();
-    m.rho_n = c->d_rho_n();
+    m.rho_n = sc.rho_n;
     m.tau1 = c->tau1;
     if (timed && c->ev_used + 2 > c->ev.size()) {
         for (int k = 0; k < 256; k++) {
@@ -318,9 +340,9 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     la.nrep = c->nrep;
     la.buf = c->d_pop(1 - c->cur);
     la.vrho = c->d_vrho();
-    la.rho_n = c->d_rho_n();
-    la.raw = c->d_raw();
-    la.part1 = c->d_part1();
+    la.rho_n = sc.rho_n;
+    la.raw = sc.raw;
+    la.part1 = sc.part1;
     e = launch_links(c->prec, la, c->k3_grid, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "link kernel launch");
     ParticleArgs pa;
@@ -329,10 +351,10 @@ int enqueue_step(lbm_ctx *c, bool timed) {
     pa.k3_begin = c->d_tables() + (c->nrep + 1);
     pa.nrep = c->nrep;
     pa.buf = c->d_pop(1 - c->cur);
-    pa.part1 = c->d_part1();
-    pa.part3 = c->d_part3();
+    pa.part1 = sc.part1;
+    pa.part3 = sc.part3;
     pa.pmask = c->d_pmask();
-    pa.raw = c->d_raw();
+    pa.raw = sc.raw;
     pa.vrho = c->d_vrho();
     pa.series = c->d_series();
     // many particle workgroups: a separate finishing launch beats one
@@ -458,6 +480,10 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
     c->ws = reinterpret_cast<char *>(dev_ws);
     c->ws_bytes = ws_bytes;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_EDEVICE, "hipGetDevice failed");
+    }
     c->L = L;
     c->desc.resize(n_replicas);
     c->tau1 = 1;
@@ -581,7 +607,7 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
                 const int parity = c->cur;
                 HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
                 int rc = LBM_OK;
-                for (int k = 0; k < c->graph_steps && rc == LBM_OK; k++) rc = enqueue_step(c, false);
+                for (int k = 0; k < c->graph_steps && rc == LBM_OK; k++) rc = enqueue_step(c, false, workspace_scratch(c));
                 hipGraph_t graph = nullptr;
                 hipError_t e = hipStreamEndCapture(c->stream, &graph);
                 c->cur = parity;  // capture only recorded the launches
@@ -599,7 +625,48 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     }
     for (int32_t k = 0; k < left; k++) {
         const bool timed = c->timing && (c->timing_step++ % c->timing_every) == 0;
-        const int rc = enqueue_step(c, timed);
+        const int rc = enqueue_step(c, timed, workspace_scratch(c));
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_step_noalloc(lbm_ctx *c, int32_t nsteps) {
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    // the per-step scratch this context needs, carved as in the workspace
+    const size_t b1 = align_up(sizeof(double) * std::max<int64_t>(c->L.part3_tot, 1));
+    const size_t b3 = b1;
+    const size_t braw = align_up(sizeof(double) * std::max<int64_t>(RAW * c->L.S3tot, 1));
+    const size_t brho = align_up(sizeof(double) * std::max<int64_t>(2 * c->L.S3tot, 1));
+    const size_t need = b1 + b3 + braw + brho;
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(c, LBM_EINVAL, fmt("lbm_step_noalloc: the context needs %zu bytes of step scratch, "
+                                       "more than the %zu of the static array", need, STATIC_SCRATCH_BYTES));
+    if (c->device < 0 || c->device >= MAX_DEVICES) return fail(c, LBM_EDEVICE, "device index out of range");
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[c->device]) {
+            int cur = 0;
+            HIP_TRY(c, hipGetDevice(&cur));
+            if (cur != c->device) HIP_TRY(c, hipSetDevice(c->device));
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (cur != c->device) HIP_TRY(c, hipSetDevice(cur));
+            if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+            g_scratch_ptr[c->device] = ptr;
+        }
+        base = reinterpret_cast<char *>(g_scratch_ptr[c->device]);
+    }
+    StepScratch sc;
+    sc.part1 = reinterpret_cast<double *>(base);
+    sc.part3 = reinterpret_cast<double *>(base + b1);
+    sc.raw = reinterpret_cast<double *>(base + b1 + b3);
+    sc.rho_n = reinterpret_cast<double *>(base + b1 + b3 + braw);
+    for (int32_t k = 0; k < nsteps; k++) {
+        const bool timed = c->timing && (c->timing_step++ % c->timing_every) == 0;
+        const int rc = enqueue_step(c, timed, sc);
         if (rc != LBM_OK) return rc;
     }
     return LBM_OK;
@@ -837,10 +904,10 @@ LBM_API int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, in
         int r = upload_desc(c);
         if (r != LBM_OK) return r;
         c->timing = false;
-        if ((r = enqueue_step(c, false)) != LBM_OK) return r;  // first launch of this shape
+        if ((r = enqueue_step(c, false, workspace_scratch(c))) != LBM_OK) return r;  // first launch of this shape
         c->timing = true;
         c->ev_used = 0;
-        for (int k = 0; k < steps_per_trial && r == LBM_OK; k++) r = enqueue_step(c, true);
+        for (int k = 0; k < steps_per_trial && r == LBM_OK; k++) r = enqueue_step(c, true, workspace_scratch(c));
         if (r != LBM_OK) return r;
         int64_t n = 0;
         return lbm_timing_read(c, &ms, &n);
@@ -980,7 +1047,7 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
             hipError_t e = launch_adj_record(c->prec, ra, c->desc[0].N, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
             int r;
-            if (k < K && (r = enqueue_step(c, false)) != LBM_OK) return r;
+            if (k < K && (r = enqueue_step(c, false, workspace_scratch(c))) != LBM_OK) return r;
         }
         return LBM_OK;
     };

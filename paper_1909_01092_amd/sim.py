@@ -93,6 +93,11 @@ class Simulation:
     def step(self, n: int = 1):
         self._check(self._lib.lbm_step(self._ctx, int(n)))
 
+    def step_noalloc(self, n: int = 1):
+        """The same steps with the library's static step scratch instead of
+        the workspace's (lbm_step_noalloc)."""
+        self._check(self._lib.lbm_step_noalloc(self._ctx, int(n)))
+
     def sync(self):
         self._check(self._lib.lbm_sync(self._ctx))
 
