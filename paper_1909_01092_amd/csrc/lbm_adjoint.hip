@@ -593,10 +593,10 @@ __global__ __launch_bounds__(NB) void k_adj_links(AdjArgs a) {
     uint32_t lk = 0;
     if (in) {
         Nbr nb;
-        nbr_of(p, sn.X, g, nb);
-        if (!pnode_nb(nb, 0, D.R2))
+        nbr_of(p, sn.X, D.R2, g, nb);
+        if (!pnode_nb(nb, 0))
             for (int i = 1; i < Q; i++)
-                if (nbr_ok(nb, i) && pnode_nb(nb, i, D.R2)) lk |= 1u << i;
+                if (nbr_ok(nb, i) && pnode_nb(nb, i)) lk |= 1u << i;
     }
     if (lk) {  // both lanes of the pair
         const int64_t n = lin(p, g);

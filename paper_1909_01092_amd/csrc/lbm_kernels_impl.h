@@ -248,17 +248,28 @@ __device__ __forceinline__ double dpp_add(double x) {
     return x + __hiloint2double(phi, plo);
 }
 
-__device__ __forceinline__ double lane_value(double x, int lane) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
-                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+// x + (x of the lane 16 or 32 apart), the lower lane's value first in every
+// lane, FP64 as two 32-bit swaps (v_permlane16_swap / v_permlane32_swap:
+// rows 0-1 and 2-3, or the two halves of the wave, exchanged)
+__device__ __forceinline__ double add_row_pair(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+__device__ __forceinline__ double add_half_pair(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
 }
 
 // Sum over the 64 lanes of a wave, in a fixed order and bitwise the same in
 // every lane: lane pairs, then quads, 8-lane halves and 16-lane rows are
 // combined with DPP permutations (quad swaps, half-row and row mirrors; each
-// step adds two equal partial sums in either order, so all lanes agree), and
-// the four row sums are read from lanes 0, 16, 32, 48 and added in order.
-// All lanes of the wave must be active.
+// step adds two equal partial sums in either order, so all lanes agree), then
+// rows 0 + 1 and 2 + 3 and the two halves with lane swaps (lower part first).
+// Everything stays in vector registers.  All lanes of the wave must be active.
 template <int NV>
 __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 #pragma unroll
@@ -268,7 +279,8 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
         x = dpp_add<0x4E>(x);   // quad_perm [2,3,0,1]
         x = dpp_add<0x141>(x);  // row_half_mirror
         x = dpp_add<0x140>(x);  // row_mirror
-        v[k] = ((lane_value(x, 0) + lane_value(x, 16)) + lane_value(x, 32)) + lane_value(x, 48);
+        x = add_row_pair(x);
+        v[k] = add_half_pair(x);
     }
 }
 
@@ -586,56 +598,78 @@ void k_main(MainArgs a) {
 // in a fixed order independent of the launch: lane l adds partials l, l + 64,
 // ..., then a butterfly over the wave.  Every lane of every wave holds the
 // same result, so no LDS or barrier is needed.
+// A lane's partials are loaded CH at a time before they are added (in the
+// same order), so a long list costs 1/CH of the dependent round trips.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double *part, int count, int k0, double (&v)[NV]) {
+    constexpr int CH = NV > 16 ? 2 : 4;
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < NV; k++) v[k] = 0.0;
-    for (int w = lane; w < count; w += 64) {
-        const double *p = part + (int64_t)w * PART + k0;
+    for (int w0 = lane; w0 < count; w0 += CH * 64) {
+        double c[CH][NV];
 #pragma unroll
-        for (int k = 0; k < NV; k++) v[k] += p[k];
+        for (int j = 0; j < CH; j++) {
+            const int w = w0 + 64 * j;
+            const double *p = part + (int64_t)(w < count ? w : 0) * PART + k0;
+#pragma unroll
+            for (int k = 0; k < NV; k++) c[j][k] = p[k];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; j++) {
+            if (w0 + 64 * j >= count) break;
+#pragma unroll
+            for (int k = 0; k < NV; k++) v[k] += c[j][k];
+        }
     }
     wave_sum<NV>(v);
 }
 
-// Neighbourhood of a box node p for the particle predicate: along each axis
-// the three positions p + {-1, 0, 1} (wrapped on periodic axes, flagged
-// outside on wall axes) with their squared minimum-image separations from a
-// centre.  pnode_nb combines them in the order pnode uses, so the decision
-// for a neighbour is bitwise the one pnode takes for it.
+// Neighbourhood of a box node p for the particle predicate: for p itself
+// (bit 0) and each neighbour p + c_i (bit i), whether it lies inside the
+// lattice (not a wall layer) and whether it is a particle node of the
+// sphere at Xc.  The squared minimum-image separations along each axis are
+// formed once for the positions p + {-1, 0, 1} (wrapped on periodic axes) and
+// combined in the order pnode uses, so every decision is bitwise the one
+// pnode takes for that node.  Held as two bit masks, not as arrays, so that
+// nothing of it is kept in scratch memory.
 struct Nbr {
-    double s[3][3];   // [axis][c + 1] squared separation
-    bool ok[3][3];    // position inside the lattice (not a wall layer)
+    uint32_t ok;      // bit i: p + c_i inside the lattice
+    uint32_t solid;   // bit i: p + c_i a particle node
 };
 
-__device__ __forceinline__ void nbr_of(const int (&p)[3], const double *Xc, const Geo &g, Nbr &nb) {
+__device__ __forceinline__ void nbr_of(const int (&p)[3], const double *Xc, double R2, const Geo &g,
+                                       Nbr &nb) {
 #pragma clang fp contract(off)
     const int n3[3] = {g.nx, g.ny, g.nz};
     const bool w3[3] = {g.wx, g.wy, g.wz};
+    double sq[3][3];
+    bool in[3][3];
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             int q = p[ax] + k - 1;
-            nb.ok[ax][k] = w3[ax] ? (q >= 0 && q < n3[ax]) : true;
+            in[ax][k] = w3[ax] ? (q >= 0 && q < n3[ax]) : true;
             if (!w3[ax]) q = q < 0 ? q + n3[ax] : (q >= n3[ax] ? q - n3[ax] : q);
             const double d = sepd((double)q - Xc[ax], n3[ax], w3[ax]);
-            nb.s[ax][k] = d * d;
+            sq[ax][k] = d * d;
         }
+    }
+    nb.ok = 0u;
+    nb.solid = 0u;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        double d2 = sq[0][cx(i) + 1] + sq[1][cy(i) + 1];
+        d2 = d2 + sq[2][cz(i) + 1];
+        if (in[0][cx(i) + 1] && in[1][cy(i) + 1] && in[2][cz(i) + 1]) nb.ok |= 1u << i;
+        if (d2 < R2) nb.solid |= 1u << i;
     }
 }
 
-__device__ __forceinline__ bool nbr_ok(const Nbr &nb, int i) {
-    return nb.ok[0][cx(i) + 1] && nb.ok[1][cy(i) + 1] && nb.ok[2][cz(i) + 1];
-}
+__device__ __forceinline__ bool nbr_ok(const Nbr &nb, int i) { return (nb.ok >> i) & 1u; }
 
-__device__ __forceinline__ bool pnode_nb(const Nbr &nb, int i, double R2) {
-#pragma clang fp contract(off)
-    double d2 = nb.s[0][cx(i) + 1] + nb.s[1][cy(i) + 1];
-    d2 = d2 + nb.s[2][cz(i) + 1];
-    return d2 < R2;
-}
+__device__ __forceinline__ bool pnode_nb(const Nbr &nb, int i) { return (nb.solid >> i) & 1u; }
 
 // box coordinates of lattice node p in the box at org (periodic axes
 // unwrapped next to it); false when p lies outside the box
@@ -700,8 +734,8 @@ __device__ __forceinline__ Rho2 mean_kept(int px, int py, int pz, Pos3 Xo, Pos3 
                                         double rho0A, double rho0B) {
     const int p[3] = {px, py, pz};
     Nbr no, nn;
-    nbr_of(p, Xo.v, g, no);
-    nbr_of(p, Xn.v, g, nn);
+    nbr_of(p, Xo.v, R2, g, no);
+    nbr_of(p, Xn.v, R2, g, nn);
     int bo[3];
     const bool inbox = box_coords(p, orgo.v, Sx, g, bo);
     int idx[Q];
@@ -709,7 +743,7 @@ __device__ __forceinline__ Rho2 mean_kept(int px, int py, int pz, Pos3 Xo, Pos3 
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         idx[i] = inbox ? box_nb(bo, i, Sx) : -1;
-        if (idx[i] >= 0 && nbr_ok(no, i) && !pnode_nb(no, i, R2) && !pnode_nb(nn, i, R2))
+        if (idx[i] >= 0 && nbr_ok(no, i) && !pnode_nb(no, i) && !pnode_nb(nn, i))
             keep |= 1u << i;
     }
     double s0 = 0.0, s1 = 0.0;
@@ -741,7 +775,8 @@ template <typename S, typename T, int B>
 __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
     __shared__ double red[(B / 64) * 16];
     const int r = find_rep(a.k3_begin, a.nrep, blockIdx.x);
-    const RepDesc D = a.desc[r];  // by value: no reload after stores
+    const RepDesc *__restrict__ dp = a.desc + r;  // read-only in this kernel
+    const RepDesc &D = *dp;
     const RepState st = a.state[r];
     if (!D.has_particle) return;
     const Geo g = geo_of(D);
@@ -763,8 +798,8 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
     int bb[3], p[3];
     const bool in = b < S3 && bbox_pos(b, org, Sx, g, bb, p);
     Nbr nb;
-    nbr_of(p, X, g, nb);
-    const bool fluid = in && !pnode_nb(nb, 0, D.R2);
+    nbr_of(p, X, D.R2, g, nb);
+    const bool fluid = in && !pnode_nb(nb, 0);
     // Loads, arithmetic and stores are kept in three separate phases: on this
     // architecture loads and stores share one wait counter, so a store issued
     // before a later load's wait would turn that wait into a write round trip.
@@ -776,7 +811,7 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
         // fluid node: links to neighbours that are particle nodes at X^n
 #pragma unroll
         for (int i = 1; i < Q; i++)
-            if (box_nb(bb, i, Sx) >= 0 && nbr_ok(nb, i) && pnode_nb(nb, i, D.R2)) links |= 1u << i;
+            if (box_nb(bb, i, Sx) >= 0 && nbr_ok(nb, i) && pnode_nb(nb, i)) links |= 1u << i;
         // plain pulls, own post-collision values (own slots are always valid,
         // so they are loaded unconditionally), own densities
         own = pidx(p[0], p[1], p[2], g);
@@ -846,7 +881,7 @@ __global__ __launch_bounds__(B) void k_links(LinkArgs a) {
         for (int k = 1; k < Q; k++) {
             rn[0][k] = rn[1][k] = 0.0;
             const int xb = box_nb(bb, k, Sx);
-            if (xb < 0 || !nbr_ok(nb, k) || pnode_nb(nb, k, D.R2)) continue;
+            if (xb < 0 || !nbr_ok(nb, k) || pnode_nb(nb, k)) continue;
             fl |= 1u << k;
             rn[0][k] = rho_n[xb];
             rn[1][k] = rho_n[S3 + xb];
@@ -995,7 +1030,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     __shared__ Rho2 job_res[64];
     const int wg = blockIdx.x;
     const int r = find_rep(a.k3_begin, a.nrep, wg);
-    const RepDesc D = a.desc[r];  // by value: no reload after stores
+    const RepDesc *__restrict__ dp = a.desc + r;  // read-only in this kernel
+    const RepDesc &D = *dp;
     RepState *st = a.state + r;
     const Geo g = geo_of(D);
     const int t = threadIdx.x;
@@ -1034,10 +1070,10 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
     int bb[3] = {0, 0, 0}, p[3] = {0, 0, 0};
     const bool in = b < S3 && bbox_pos(b, org, Sx, g, bb, p);
     Nbr no, nn;
-    nbr_of(p, X, g, no);
-    nbr_of(p, Xn, g, nn);
-    const bool fo = in && !pnode_nb(no, 0, D.R2);
-    const bool fn = in && !pnode_nb(nn, 0, D.R2);
+    nbr_of(p, X, D.R2, g, no);
+    nbr_of(p, Xn, D.R2, g, nn);
+    const bool fo = in && !pnode_nb(no, 0);
+    const bool fn = in && !pnode_nb(nn, 0);
     int bo[3];
     const bool inbox = box_coords(p, orgo, Sx, g, bo);
     // Loads and arithmetic first, every store last (loads and stores share
@@ -1058,8 +1094,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             idx[i] = -1;
-            if (!nbr_ok(nn, i) || pnode_nb(nn, i, D.R2)) continue;
-            if (pnode_nb(no, i, D.R2)) {
+            if (!nbr_ok(nn, i) || pnode_nb(nn, i)) continue;
+            if (pnode_nb(no, i)) {
                 fresh |= 1u << i;
             } else {
                 idx[i] = inbox ? box_nb(bo, i, Sx) : -1;
@@ -1218,7 +1254,8 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
 template <int B>
 __global__ __launch_bounds__(B) void k_finish(ParticleArgs a) {
     const int r = blockIdx.x;
-    const RepDesc D = a.desc[r];
+    const RepDesc *__restrict__ dp = a.desc + r;  // read-only in this kernel
+    const RepDesc &D = *dp;
     RepState *st = a.state + r;
     if (!D.has_particle) {
         if (threadIdx.x == 0) advance_empty(a, D, st);
