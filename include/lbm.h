@@ -266,6 +266,22 @@ int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_t *bytes
 int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
                 double grad[5], double *J);
 
+/* The two halves of lbm_adjoint, for a caller (an autograd function) that
+ * needs J now and the gradient only later.
+ * lbm_adjoint_forward: the forward sweep alone (the nsteps steps with the
+ * checkpoints and the recorded last segment, about the cost of nsteps plain
+ * steps); *J = the mean of U_z^{n+1/2} over those steps (from the running
+ * sum the step keeps).  The context then holds the state after the steps and
+ * a tape in dev_adj, which the caller keeps alive and untouched.
+ * lbm_adjoint_backward: the reverse sweep over that tape; grad[5] as for
+ * lbm_adjoint; the context is left where the forward sweep left it.  One
+ * backward per forward; LBM_ESTATE when no tape is pending or the context
+ * was stepped, restored or autotuned since the forward sweep.  Arguments,
+ * requirements and errors of the forward sweep are those of lbm_adjoint. */
+int lbm_adjoint_forward(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
+                        double *J);
+int lbm_adjoint_backward(lbm_ctx *c, double grad[5]);
+
 void lbm_destroy(lbm_ctx *c);
 const char *lbm_last_error(const lbm_ctx *c);  /* NULL ctx: last lbm_init error */
 

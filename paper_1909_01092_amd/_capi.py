@@ -73,6 +73,8 @@ SIGNATURES = {
     "lbm_step_bytes": (C.c_int, [_V, _D]),
     "lbm_adjoint_bytes": (C.c_int, [_V, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "lbm_adjoint": (C.c_int, [_V, C.c_int32, C.c_int32, _V, C.c_size_t, _D, _D]),
+    "lbm_adjoint_forward": (C.c_int, [_V, C.c_int32, C.c_int32, _V, C.c_size_t, _D]),
+    "lbm_adjoint_backward": (C.c_int, [_V, _D]),
     "lbm_destroy": (None, [_V]),
     "lbm_last_error": (C.c_char_p, [_V]),
 }

@@ -15,6 +15,10 @@ from .sim import Simulation
 
 
 class SettlingVelocity(torch.autograd.Function):
+    """forward runs the steps once (lbm_adjoint_forward: checkpoints and the
+    recorded last segment) and keeps the run; backward runs the reverse sweep
+    over it (lbm_adjoint_backward) and releases it."""
+
     @staticmethod
     def forward(ctx, theta, params, nsteps, precision="fp32", segment=0):
         th = theta.detach().to("cpu", torch.float64).numpy()
@@ -24,16 +28,24 @@ class SettlingVelocity(torch.autograd.Function):
         p["wet_drho"] = float(th[4])
         sim = Simulation(p, precision)
         try:
-            J, grad = sim.adjoint(int(nsteps), int(segment))
-        finally:
+            J = sim.adjoint_forward(int(nsteps), int(segment))
+        except Exception:
             sim.close()
-        ctx.save_for_backward(torch.as_tensor(np.asarray(grad), dtype=theta.dtype))
+            raise
+        ctx.sim = sim
+        ctx.theta_dtype = theta.dtype
         return theta.new_tensor(J)
 
     @staticmethod
     def backward(ctx, gJ):
-        (grad,) = ctx.saved_tensors
-        return gJ.to("cpu") * grad, None, None, None, None
+        sim = ctx.sim
+        ctx.sim = None
+        try:
+            grad = sim.adjoint_backward()
+        finally:
+            sim.close()
+        g = torch.as_tensor(np.asarray(grad), dtype=ctx.theta_dtype)
+        return gJ.to("cpu") * g, None, None, None, None
 
 
 def settling_velocity(theta, params, nsteps, precision="fp32", segment=0):

@@ -187,6 +187,14 @@ struct lbm_ctx {
     int64_t timing_step = 0;  // plain-launch steps since timing was enabled
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
+    // adjoint tape left by lbm_adjoint_forward for lbm_adjoint_backward
+    struct {
+        bool valid = false;
+        int32_t nsteps = 0, segment = 0;
+        char *buf = nullptr;
+        size_t bytes = 0;
+        int64_t step_end = 0;
+    } tape;
     std::string err;
 
     RepDesc *d_desc() { return reinterpret_cast<RepDesc *>(ws + L.desc); }
@@ -599,6 +607,7 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
 LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    c->tape.valid = false;
     int32_t left = nsteps;
     if (c->graph_steps > 0 && !c->timing) {
         while (left >= c->graph_steps) {
@@ -634,6 +643,7 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
 LBM_API int lbm_step_noalloc(lbm_ctx *c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    c->tape.valid = false;
     // the per-step scratch this context needs, carved as in the workspace
     const size_t b1 = align_up(sizeof(double) * std::max<int64_t>(c->L.part3_tot, 1));
     const size_t b3 = b1;
@@ -850,6 +860,7 @@ LBM_API int lbm_checkpoint(lbm_ctx *c, void *dev_dst) {
 
 LBM_API int lbm_restore(lbm_ctx *c, const void *dev_src) {
     if (!c || !dev_src) return LBM_EINVAL;
+    c->tape.valid = false;
     const char *d = reinterpret_cast<const char *>(dev_src);
     const size_t pb = 38 * c->L.NPtot * c->es, sb = sizeof(RepState) * c->nrep;
     HIP_TRY(c, hipMemcpyAsync(c->d_pop(c->cur), d, pb, hipMemcpyDeviceToDevice, c->stream));
@@ -888,6 +899,7 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk) {
 LBM_API int lbm_autotune(lbm_ctx *c, int32_t steps_per_trial, void *dev_ckpt, int32_t *block_out,
                          int32_t *zchunk_out, double *best_ms) {
     if (!c) return LBM_EINVAL;
+    c->tape.valid = false;
     if (steps_per_trial < 1) return fail(c, LBM_EINVAL, "steps_per_trial must be >= 1");
     int rc = LBM_OK;
     if (dev_ckpt && (rc = lbm_checkpoint(c, dev_ckpt)) != LBM_OK) return rc;
@@ -1006,11 +1018,35 @@ LBM_API int lbm_adjoint_bytes(lbm_ctx *c, int32_t nsteps, int32_t segment, size_
     return LBM_OK;
 }
 
-LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
-                        double grad[5], double *J) {
+namespace {
+// K steps from the current state, recording the moments and the sphere
+// state before every step and after the last (into the tape's record area)
+int record_segment(lbm_ctx *c, const AdjLayout &A, char *w, RepState *rst, int K) {
+    for (int k = 0; k <= K; k++) {
+        RecArgs ra;
+        ra.desc = c->d_desc();
+        ra.state = c->d_state();
+        ra.src = c->d_pop(c->cur);
+        ra.rec = w + A.rec + (size_t)k * A.recb;
+        ra.st_out = rst + k;
+        hipError_t e = launch_adj_record(c->prec, ra, c->desc[0].N, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
+        int r;
+        if (k < K && (r = enqueue_step(c, false, workspace_scratch(c))) != LBM_OK) return r;
+    }
+    return LBM_OK;
+}
+}  // namespace
+
+namespace {
+// Forward sweep of the adjoint form: nsteps steps from the current state with
+// a checkpoint at the start of every segment and after the last step; the
+// last segment's moments and sphere states are recorded on the way.  Leaves
+// the context after the nsteps steps and the tape for adjoint_backward.
+int adjoint_forward(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes, double *J) {
+    c->tape.valid = false;
     int rc = adj_check(c, nsteps, segment);
     if (rc != LBM_OK) return rc;
-    if (!grad || !J) return fail(c, LBM_EINVAL, "grad and J must not be NULL");
     const AdjLayout A = adj_plan(c, nsteps, segment);
     if (!dev_adj || ((uintptr_t)dev_adj % ALIGN) != 0)
         return fail(c, LBM_ENOMEM, "adjoint buffer must be a 256-byte aligned device pointer");
@@ -1022,8 +1058,48 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     if (rc != LBM_OK) return rc;
     if (st0.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run is unstable");
     char *w = reinterpret_cast<char *>(dev_adj);
-    // with timing on, the timed launches of this call are the adjoint node
-    // kernel's (the forward sweep and the replays run untimed)
+    struct TimingOff {
+        lbm_ctx *c;
+        bool was;
+        ~TimingOff() { c->timing = was; }
+    } keep{c, c->timing};
+    c->timing = false;
+    auto ck = [&](int s) { return w + A.ck + (size_t)s * A.ckb; };
+    auto seg_len = [&](int s) { return std::min(A.seg, nsteps - s * A.seg); };
+    RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
+    for (int s = 0; s < A.nseg; s++) {
+        if ((rc = lbm_checkpoint(c, ck(s))) != LBM_OK) return rc;
+        rc = s + 1 < A.nseg ? lbm_step(c, seg_len(s)) : record_segment(c, A, w, rst, seg_len(s));
+        if (rc != LBM_OK) return rc;
+    }
+    if ((rc = lbm_checkpoint(c, ck(A.nseg))) != LBM_OK) return rc;
+    RepState st1;
+    if ((rc = read_state(c, 0, &st1)) != LBM_OK) return rc;
+    if (J) *J = (st1.uz_sum - st0.uz_sum) / nsteps;
+    if (st1.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run went unstable");
+    c->tape.valid = true;
+    c->tape.nsteps = nsteps;
+    c->tape.segment = segment;
+    c->tape.buf = w;
+    c->tape.bytes = adj_bytes;
+    c->tape.step_end = st1.step;
+    return LBM_OK;
+}
+
+// Reverse sweep over the tape of adjoint_forward: last segment first, each
+// segment's steps reversed, every other segment replayed from its checkpoint
+// and recorded first.  Leaves the context where the forward sweep left it.
+int adjoint_backward(lbm_ctx *c, double grad[5], double *J) {
+    if (!c->tape.valid) return fail(c, LBM_ESTATE, "no adjoint tape: call lbm_adjoint_forward first");
+    const int32_t nsteps = c->tape.nsteps;
+    const AdjLayout A = adj_plan(c, nsteps, c->tape.segment);
+    char *w = c->tape.buf;
+    RepState stc;
+    int rc = read_state(c, 0, &stc);
+    if (rc != LBM_OK) return rc;
+    if (stc.step != c->tape.step_end)
+        return fail(c, LBM_ESTATE, "the context moved since lbm_adjoint_forward");
+    c->tape.valid = false;  // the sweep replays and restores: one backward per forward
     const bool timed = c->timing;
     struct TimingOff {
         lbm_ctx *c;
@@ -1034,31 +1110,6 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     auto ck = [&](int s) { return w + A.ck + (size_t)s * A.ckb; };
     auto seg_len = [&](int s) { return std::min(A.seg, nsteps - s * A.seg); };
     RepState *rst = reinterpret_cast<RepState *>(w + A.rst);
-    // K steps from the current state, recording the moments and the sphere
-    // state before every step and after the last
-    auto record_segment = [&](int K) -> int {
-        for (int k = 0; k <= K; k++) {
-            RecArgs ra;
-            ra.desc = c->d_desc();
-            ra.state = c->d_state();
-            ra.src = c->d_pop(c->cur);
-            ra.rec = w + A.rec + (size_t)k * A.recb;
-            ra.st_out = rst + k;
-            hipError_t e = launch_adj_record(c->prec, ra, c->desc[0].N, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint record launch");
-            int r;
-            if (k < K && (r = enqueue_step(c, false, workspace_scratch(c))) != LBM_OK) return r;
-        }
-        return LBM_OK;
-    };
-    // forward sweep: a checkpoint at the start of every segment and at the
-    // end; the last segment is recorded on the way, so it is not replayed
-    for (int s = 0; s < A.nseg; s++) {
-        if ((rc = lbm_checkpoint(c, ck(s))) != LBM_OK) return rc;
-        rc = s + 1 < A.nseg ? lbm_step(c, seg_len(s)) : record_segment(seg_len(s));
-        if (rc != LBM_OK) return rc;
-    }
-    if ((rc = lbm_checkpoint(c, ck(A.nseg))) != LBM_OK) return rc;
     HIP_TRY(c, hipMemsetAsync(w + A.adj, 0, sizeof(AdjState), c->stream));
     HIP_TRY(c, hipMemsetAsync(w + A.A[0], 0, A.Ab, c->stream));
 
@@ -1092,7 +1143,7 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
         const int K = seg_len(s);
         if (s + 1 < A.nseg) {  // replay (the last segment was recorded by the sweep)
             if ((rc = lbm_restore(c, ck(s))) != LBM_OK) return rc;
-            if ((rc = record_segment(K)) != LBM_OK) return rc;
+            if ((rc = record_segment(c, A, w, rst, K)) != LBM_OK) return rc;
         }
         for (int k = K - 1; k >= 0; k--) {
             aa.stn = rst + k;
@@ -1127,10 +1178,35 @@ LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
     for (int a = 0; a < 3; a++) grad[a] = h.grad[a] + caf * h.afb[a];
     grad[3] = h.grad[3];
     grad[4] = h.grad[4];
-    *J = h.Jsum / nsteps;
+    if (J) *J = h.Jsum / nsteps;
     if (st1.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "the run went unstable");
     return LBM_OK;
 }
+}  // namespace
+
+LBM_API int lbm_adjoint_forward(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
+                                double *J) {
+    if (!c) return LBM_EINVAL;
+    if (!J) return fail(c, LBM_EINVAL, "J must not be NULL");
+    return adjoint_forward(c, nsteps, segment, dev_adj, adj_bytes, J);
+}
+
+LBM_API int lbm_adjoint_backward(lbm_ctx *c, double grad[5]) {
+    if (!c) return LBM_EINVAL;
+    if (!grad) return fail(c, LBM_EINVAL, "grad must not be NULL");
+    return adjoint_backward(c, grad, nullptr);
+}
+
+LBM_API int lbm_adjoint(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_adj, size_t adj_bytes,
+                        double grad[5], double *J) {
+    if (!c) return LBM_EINVAL;
+    if (!grad || !J) return fail(c, LBM_EINVAL, "grad and J must not be NULL");
+    int rc = adjoint_forward(c, nsteps, segment, dev_adj, adj_bytes, nullptr);
+    if (rc != LBM_OK) return rc;
+    return adjoint_backward(c, grad, J);
+}
+
+
 
 LBM_API void lbm_destroy(lbm_ctx *c) {
     if (!c) return;

@@ -1009,6 +1009,7 @@ __device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDes
         st->Lev[q] = tot[3 + q] - utot[3 + q];
         st->org[q] = mo.org[q];
         s[q] = mo.Un[q];
+        if (q == 2) st->uz_sum += mo.Un[2];
         if (!(fabs(mo.Un[q]) < 0.5) || !isfinite(mo.F[q])) bad = true;
         if (w3[q] && (mo.Xn[q] - D.radius < -0.5 || mo.Xn[q] + D.radius > n3[q] - 0.5)) bad = true;
     }

@@ -66,7 +66,7 @@ struct RepState {
     double Pev[3], Lev[3];   // pending cover/uncover momentum, angular momentum
     double delta[2];         // mass correction applied when pulling step n
     double n_fluid;
-    double pad0;
+    double uz_sum;           // running sum of U_z^{n+1/2} over the steps taken
     int64_t step, n_cov, n_unc, n_links;
     int32_t org[3];          // origin of the bounding box of X^n
     int32_t pad_org;

@@ -214,6 +214,30 @@ class Simulation:
                                           grad.ctypes.data_as(C.POINTER(C.c_double)), C.byref(J)))
         return J.value, grad
 
+    def adjoint_forward(self, nsteps: int, segment: int = 0) -> float:
+        """Forward sweep of the adjoint form alone (lbm_adjoint_forward):
+        advance nsteps with checkpoints and return J; the tape stays in a
+        buffer this object holds until adjoint_backward."""
+        import torch
+        n = C.c_size_t()
+        self._check(self._lib.lbm_adjoint_bytes(self._ctx, int(nsteps), int(segment), C.byref(n)))
+        self._tape = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._tape.data_ptr() + 255) // 256 * 256
+        J = C.c_double()
+        self._check(self._lib.lbm_adjoint_forward(self._ctx, int(nsteps), int(segment), C.c_void_p(ptr),
+                                                  n.value, C.byref(J)))
+        return J.value
+
+    def adjoint_backward(self) -> np.ndarray:
+        """Reverse sweep over the tape of the last adjoint_forward
+        (lbm_adjoint_backward): dJ/d(g_x, g_y, g_z, G, Delta rho)."""
+        grad = np.empty(5)
+        try:
+            self._check(self._lib.lbm_adjoint_backward(self._ctx, grad.ctypes.data_as(C.POINTER(C.c_double))))
+        finally:
+            self._tape = None
+        return grad
+
     # -- checkpoints (device tensors)
     def checkpoint(self):
         import torch

@@ -191,3 +191,72 @@ def test_adjoint_with_graph(Sim):
     b.set_graph(4)
     Jb, gb = b.adjoint(steps, 10)
     assert Ja == Jb and np.array_equal(ga, gb)
+
+
+def test_split_adjoint_equals_the_whole_call(Sim):
+    """lbm_adjoint_forward then lbm_adjoint_backward give the gradient of
+    lbm_adjoint bit for bit, J to rounding (a running sum instead of the
+    reverse sweep's), and leave the context where lbm_adjoint leaves it."""
+    import torch
+    steps, seg = 24, 10
+    a = Sim(EVENTS, "fp64", stream=torch.cuda.Stream())
+    Ja, ga = a.adjoint(steps, seg)
+    b = Sim(EVENTS, "fp64", stream=torch.cuda.Stream())
+    Jb = b.adjoint_forward(steps, seg)
+    fb_mid = b.populations()
+    gb = b.adjoint_backward()
+    print(f"split J {Jb:.15e} whole {Ja:.15e}", flush=True)
+    assert abs(Jb - Ja) <= 1e-13 * abs(Ja)
+    assert np.array_equal(ga, gb)
+    fa, fb = a.populations(), b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(fb, fb_mid)
+    assert a.particle_state()["step"] == b.particle_state()["step"] == steps
+
+
+def test_adjoint_backward_needs_its_forward(Sim):
+    """No tape, or a context stepped after the forward sweep: LBM_ESTATE."""
+    from paper_1909_01092_amd._capi import LBM_ESTATE, LbmError
+    sim = Sim(EVENTS, "fp32")
+    with pytest.raises(LbmError) as e:
+        sim.adjoint_backward()
+    assert e.value.code == LBM_ESTATE
+    sim.adjoint_forward(8, 4)
+    sim.step(1)
+    with pytest.raises(LbmError) as e:
+        sim.adjoint_backward()
+    assert e.value.code == LBM_ESTATE
+    sim.adjoint_forward(8, 4)
+    g = sim.adjoint_backward()
+    assert np.all(np.isfinite(g))
+
+
+def test_adjoint_forward_costs_about_plain_steps(Sim):
+    """The 48 x 48 x 192 adjoint workload (FP32, 200 steps, checkpoints every
+    50): the forward sweep alone costs about as much as 200 plain steps (its
+    extra work is four state copies and the last segment's recording); the
+    whole call costs more."""
+    import time
+    import torch
+    steps = 200
+    sim = Sim(workloads.ADJOINT, "fp32", stream=torch.cuda.Stream())
+    sim.step(20)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    plain = time.perf_counter() - t0
+    sim.adjoint_forward(50, 50)  # warm-up
+    sim.adjoint_backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.adjoint_forward(steps, 50)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim.adjoint_backward()
+    torch.cuda.synchronize()
+    bwd = time.perf_counter() - t0
+    print(f"plain {plain * 1e3:.2f} ms, forward sweep {fwd * 1e3:.2f} ms ({fwd / plain:.3f} x), "
+          f"backward {bwd * 1e3:.2f} ms ({bwd / plain:.3f} x)", flush=True)
+    assert fwd < 1.3 * plain
+    assert bwd > fwd
