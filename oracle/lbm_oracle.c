@@ -102,11 +102,15 @@ struct orc_sim {
     double *jm;         /* [2][3][N]                         */
     double *rt;         /* [2][N] densities seen by SC force */
     double *F;          /* [2][3][N]                         */
-    unsigned char *solid;     /* particle nodes at X^n       */
-    unsigned char *solid_new; /* particle nodes at X^{n+1}   */
-    orc_particle P;
+    /* particle nodes at X^n / X^{n+1}: 0 fluid, k + 1 inside sphere k (the
+     * first sphere that contains the node)                                  */
+    unsigned char *solid;
+    unsigned char *solid_new;
+    int K;                              /* spheres (0: none)                  */
+    double Rk[ORC_MAX_EXTRA + 1], rhopk[ORC_MAX_EXTRA + 1], drhok[ORC_MAX_EXTRA + 1];
+    orc_particle P[ORC_MAX_EXTRA + 1];  /* sphere states (global fields alike) */
     double M_fluid0;
-    double *series;     /* U^{n+1/2}, 3 per step             */
+    double *series[ORC_MAX_EXTRA + 1];  /* U^{n+1/2} of each sphere, 3 per step */
     int64_t series_len, series_cap;
 };
 
@@ -164,6 +168,26 @@ static int particle_node(const orc_sim *s, int x, int y, int z, const double X[3
     double d2 = r[0] * r[0] + r[1] * r[1];
     d2 = d2 + r[2] * r[2];
     return d2 < s->p.radius * s->p.radius;
+}
+
+/* the same predicate for sphere k */
+static int sphere_node(const orc_sim *s, int k, int x, int y, int z, const double X[3]) {
+    double r[3];
+    separation(s, (double)x, (double)y, (double)z, X, r);
+    double d2 = r[0] * r[0] + r[1] * r[1];
+    d2 = d2 + r[2] * r[2];
+    return d2 < s->Rk[k] * s->Rk[k];
+}
+
+/* 0 for a fluid node, else 1 + the first sphere (centres Xs[k]) containing it */
+static unsigned char owner_of(const orc_sim *s, int x, int y, int z, const orc_particle *Ps) {
+    for (int k = 0; k < s->K; k++)
+        if (sphere_node(s, k, x, y, z, Ps[k].X)) return (unsigned char)(k + 1);
+    return 0;
+}
+
+static double sphere_volume(const orc_sim *s, int k) {
+    return 4.0 / 3.0 * M_PI * s->Rk[k] * s->Rk[k] * s->Rk[k];
 }
 
 static void cross(const double a[3], const double b[3], double c[3]) {
@@ -254,14 +278,29 @@ orc_sim *orc_create(const orc_params *p) {
     s->F = (double *)calloc((size_t)(6 * N), sizeof(double));
     s->solid = (unsigned char *)calloc((size_t)N, 1);
     s->solid_new = (unsigned char *)calloc((size_t)N, 1);
+    s->K = p->radius > 0.0 ? 1 + (p->n_extra > 0 ? (p->n_extra < ORC_MAX_EXTRA ? p->n_extra : ORC_MAX_EXTRA) : 0) : 0;
     s->series_cap = 1024;
-    s->series = (double *)calloc((size_t)(3 * s->series_cap), sizeof(double));
-
-    for (int a = 0; a < 3; a++) {
-        s->P.X[a] = p->X0[a];
-        s->P.U[a] = p->U0[a];
-        s->P.W[a] = p->W0[a];
+    for (int k = 0; k < s->K || k == 0; k++)
+        s->series[k] = (double *)calloc((size_t)(3 * s->series_cap), sizeof(double));
+    for (int k = 0; k < s->K; k++) {
+        const orc_sphere e0 = {p->radius, p->rho_p, p->wet_drho, {p->X0[0], p->X0[1], p->X0[2]},
+                               {p->U0[0], p->U0[1], p->U0[2]}, {p->W0[0], p->W0[1], p->W0[2]}};
+        const orc_sphere *e = k == 0 ? &e0 : &p->extra[k - 1];
+        s->Rk[k] = e->radius;
+        s->rhopk[k] = e->rho_p;
+        s->drhok[k] = e->wet_drho;
+        for (int a = 0; a < 3; a++) {
+            s->P[k].X[a] = e->X0[a];
+            s->P[k].U[a] = e->U0[a];
+            s->P[k].W[a] = e->W0[a];
+        }
     }
+    if (s->K == 0)
+        for (int a = 0; a < 3; a++) {
+            s->P[0].X[a] = p->X0[a];
+            s->P[0].U[a] = p->U0[a];
+            s->P[0].W[a] = p->W0[a];
+        }
     /* initial particle nodes and densities rho_l0 + amp (2u - 1) (Philox tag 1) */
     uint32_t key[2];
     philox_key(s, key);
@@ -270,7 +309,7 @@ orc_sim *orc_create(const orc_params *p) {
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
                 int64_t n = node_index(s, x, y, z);
-                s->solid[n] = (unsigned char)particle_node(s, x, y, z, s->P.X);
+                s->solid[n] = owner_of(s, x, y, z, s->P);
                 if (s->solid[n]) continue;
                 uint32_t ctr[4] = {(uint32_t)n, 0u, 0u, 1u}, w[4];
                 orc_philox4x32_10(ctr, key, w);
@@ -282,15 +321,17 @@ orc_sim *orc_create(const orc_params *p) {
                     for (int i = 0; i < Q; i++) s->f[((int64_t)l * Q + i) * N + n] = s->W[i] * r;
                     s->M_fluid0 += r;
                 }
-                s->P.n_fluid += 1.0;
+                s->P[0].n_fluid += 1.0;
             }
+    for (int k = 1; k < s->K; k++) s->P[k].n_fluid = s->P[0].n_fluid;
     return s;
 }
 
 void orc_destroy(orc_sim *s) {
     if (!s) return;
     free(s->f); free(s->fpost); free(s->fnew); free(s->rho); free(s->jm);
-    free(s->rt); free(s->F); free(s->solid); free(s->solid_new); free(s->series);
+    free(s->rt); free(s->F); free(s->solid); free(s->solid_new);
+    for (int k = 0; k <= ORC_MAX_EXTRA; k++) free(s->series[k]);
     free(s);
 }
 
@@ -343,8 +384,9 @@ static void virtual_densities(orc_sim *s) {
                     cnt++;
                 }
                 if (cnt > 0) {
-                    s->rt[n] = sum[0] / cnt + p->wet_drho;
-                    s->rt[N + n] = sum[1] / cnt - p->wet_drho;
+                    const double drho = s->drhok[s->solid[n] - 1];
+                    s->rt[n] = sum[0] / cnt + drho;
+                    s->rt[N + n] = sum[1] / cnt - drho;
                 } else {
                     s->rt[n] = 0.0;
                     s->rt[N + n] = 0.0;
@@ -352,19 +394,22 @@ static void virtual_densities(orc_sim *s) {
             }
 }
 
-/* body-force acceleration of the fluid and external force on the particle */
-static void driving(const orc_sim *s, double af[3], double Fext[3]) {
+/* body-force acceleration of the fluid and external force on each sphere
+ * (Fext[k][3]); with several spheres the fluid balances their sum        */
+static void driving(const orc_sim *s, double af[3], double Fext[][3]) {
     const orc_params *p = &s->p;
-    double V = p->radius > 0.0 ? particle_volume(s) : 0.0;
     double rho_tot0 = p->rho0[0] + p->rho0[1];
-    for (int a = 0; a < 3; a++) {
-        if (p->force_mode == 1) {
-            af[a] = p->g[a];
-            Fext[a] = V * p->rho_p * p->g[a];
-        } else {
-            Fext[a] = V * (p->rho_p - rho_tot0) * p->g[a];
-            af[a] = s->M_fluid0 > 0.0 ? -Fext[a] / s->M_fluid0 : 0.0;
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < s->K; k++) {
+        double V = sphere_volume(s, k);
+        for (int a = 0; a < 3; a++) {
+            Fext[k][a] = p->force_mode == 1 ? V * s->rhopk[k] * p->g[a] : V * (s->rhopk[k] - rho_tot0) * p->g[a];
+            tot[a] += Fext[k][a];
         }
+    }
+    for (int a = 0; a < 3; a++) {
+        if (p->force_mode == 1) af[a] = p->g[a];
+        else af[a] = s->M_fluid0 > 0.0 ? -tot[a] / s->M_fluid0 : 0.0;
     }
 }
 
@@ -373,18 +418,18 @@ static void driving(const orc_sim *s, double af[3], double Fext[3]) {
  * Wall layers mirror the adjacent fluid node (neutral walls).  The share
  * of the force coming from particle nodes is returned for the reaction
  * on the particle (force Fv, torque Tv about X^n).                       */
-static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3]) {
+static void forces_impl(const orc_sim *s, double *F, double Fv[][3], double Tv[][3]) {
     int64_t N = s->N;
     const orc_params *p = &s->p;
-    double af[3], Fext[3];
+    const int K = s->K > 0 ? s->K : 1;
+    double af[3], Fext[ORC_MAX_EXTRA + 1][3];
     driving(s, af, Fext);
-    /* per-plane sums of the particle-node share: [nz][6] = Fv, Tv */
-    double *pv = (double *)calloc((size_t)p->nz * 6, sizeof(double));
+    /* per-plane sums of the particle-node share: [nz][K][6] = Fv, Tv of each sphere */
+    double *pv = (double *)calloc((size_t)p->nz * K * 6, sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
-                double *Fvz = pv + (int64_t)z * 6, *Tvz = Fvz + 3;
                 int64_t n = node_index(s, x, y, z);
                 for (int l = 0; l < 2; l++)
                     for (int a = 0; a < 3; a++) F[(l * 3 + a) * N + n] = 0.0;
@@ -407,10 +452,12 @@ static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3])
                         }
                     }
                     if (inside && s->solid[m]) {
+                        const int k = s->solid[m] - 1;
+                        double *Fvz = pv + ((int64_t)z * K + k) * 6, *Tvz = Fvz + 3;
                         double fl[3], r[3], t[3];
                         for (int a = 0; a < 3; a++) fl[a] = link[0][a] + link[1][a];
                         separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
-                                   s->P.X, r);
+                                   s->P[k].X, r);
                         cross(r, fl, t);
                         for (int a = 0; a < 3; a++) { Fvz[a] += fl[a]; Tvz[a] += t[a]; }
                     }
@@ -419,9 +466,13 @@ static void forces_impl(const orc_sim *s, double *F, double Fv[3], double Tv[3])
                     for (int a = 0; a < 3; a++)
                         F[(l * 3 + a) * N + n] = sumo[l][a] + s->rho[l * N + n] * af[a];
             }
-    for (int a = 0; a < 3; a++) { Fv[a] = 0.0; Tv[a] = 0.0; }
-    for (int z = 0; z < p->nz; z++)
-        for (int a = 0; a < 3; a++) { Fv[a] += pv[z * 6 + a]; Tv[a] += pv[z * 6 + 3 + a]; }
+    for (int k = 0; k < K; k++) {
+        for (int a = 0; a < 3; a++) { Fv[k][a] = 0.0; Tv[k][a] = 0.0; }
+        for (int z = 0; z < p->nz; z++) {
+            const double *v = pv + ((int64_t)z * K + k) * 6;
+            for (int a = 0; a < 3; a++) { Fv[k][a] += v[a]; Tv[k][a] += v[3 + a]; }
+        }
+    }
     free(pv);
 }
 
@@ -429,7 +480,7 @@ void orc_forces(const orc_sim *s, double *F) {
     orc_sim *m = (orc_sim *)s; /* moments / virtual densities are scratch */
     moments(m);
     virtual_densities(m);
-    double Fv[3], Tv[3];
+    double Fv[ORC_MAX_EXTRA + 1][3], Tv[ORC_MAX_EXTRA + 1][3];
     forces_impl(s, F, Fv, Tv);
 }
 
@@ -521,7 +572,7 @@ static void collide(orc_sim *s) {
             for (int i = 0; i < Q; i++) fin[l][i] = FI(s->f, l, i, n);
             for (int a = 0; a < 3; a++) F[l][a] = s->F[(l * 3 + a) * N + n];
         }
-        if (s->p.kT > 0.0) orc_normals(s, n, s->P.step, z);
+        if (s->p.kT > 0.0) orc_normals(s, n, s->P[0].step, z);
         else memcpy(z, zero, sizeof(z));
         orc_collide_node(s, fin, F, z, fout);
         for (int l = 0; l < 2; l++)
@@ -532,30 +583,33 @@ static void collide(orc_sim *s) {
 static void series_push(orc_sim *s) {
     if (s->series_len == s->series_cap) {
         s->series_cap *= 2;
-        s->series = (double *)realloc(s->series, (size_t)(3 * s->series_cap) * sizeof(double));
+        for (int k = 0; k < s->K || k == 0; k++)
+            s->series[k] = (double *)realloc(s->series[k], (size_t)(3 * s->series_cap) * sizeof(double));
     }
-    for (int a = 0; a < 3; a++) s->series[3 * s->series_len + a] = s->P.U[a];
+    for (int k = 0; k < s->K || k == 0; k++)
+        for (int a = 0; a < 3; a++) s->series[k][3 * s->series_len + a] = s->P[k].U[a];
     s->series_len++;
 }
 
 /* ------------------------------------------------------------ step 7
  * Streaming of fpost into fnew with half-way bounce-back on walls and
  * moving-wall bounce-back on particle nodes (momentum exchange per link:
- * dp, torque dl about X^n, bounce-back mass flux dMbb).  Returns the
- * number of boundary links.                                             */
-static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb[2]) {
+ * dp[k], torque dl[k] about X_k^n of the sphere k that owns the particle
+ * node, bounce-back mass flux dMbb).  links[k]: boundary links of sphere k. */
+static void stream_bounce(orc_sim *s, double dp[][3], double dl[][3], double dMbb[2], int64_t *links) {
     int64_t N = s->N;
     const orc_params *p = &s->p;
-    const orc_particle *P = &s->P;
+    const int K = s->K > 0 ? s->K : 1;
+    const int NV = 7 * K + 2;  /* per plane: dp, dl, links of each sphere; dMbb */
     memset(s->fnew, 0, (size_t)(2 * Q * N) * sizeof(double));
-    /* per-plane sums [nz][9] = dp, dl, dMbb, links; every destination slot
-     * has exactly one writer, so planes stream independently */
-    double *pv = (double *)calloc((size_t)p->nz * 9, sizeof(double));
+    /* per-plane sums; every destination slot has exactly one writer, so
+     * planes stream independently */
+    double *pv = (double *)calloc((size_t)p->nz * NV, sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
-                double *dpz = pv + (int64_t)z * 9, *dlz = dpz + 3, *dMz = dpz + 6;
+                double *vz = pv + (int64_t)z * NV, *dMz = vz + 7 * K;
                 int64_t n = node_index(s, x, y, z);
                 if (s->solid[n]) continue;
                 for (int l = 0; l < 2; l++) FI(s->fnew, l, 0, n) = FI(s->fpost, l, 0, n);
@@ -568,6 +622,9 @@ static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb
                     }
                     int64_t m = node_index(s, xn, yn, zn);
                     if (s->solid[m]) {
+                        const int k = s->solid[m] - 1;
+                        const orc_particle *P = &s->P[k];
+                        double *dpz = vz + 7 * k, *dlz = dpz + 3;
                         double r[3], w[3], ub[3];
                         separation(s, x + 0.5 * CV[i][0], y + 0.5 * CV[i][1], z + 0.5 * CV[i][2],
                                    P->X, r);
@@ -585,58 +642,63 @@ static int64_t stream_bounce(orc_sim *s, double dp[3], double dl[3], double dMbb
                         double t[3];
                         cross(r, lp, t);
                         for (int a = 0; a < 3; a++) { dpz[a] += lp[a]; dlz[a] += t[a]; }
-                        dMz[2] += 1.0;
+                        dpz[6] += 1.0;
                         continue;
                     }
                     for (int l = 0; l < 2; l++) FI(s->fnew, l, i, m) = FI(s->fpost, l, i, n);
                 }
             }
-    for (int a = 0; a < 3; a++) { dp[a] = 0.0; dl[a] = 0.0; }
     dMbb[0] = dMbb[1] = 0.0;
-    int64_t links = 0;
+    for (int k = 0; k < K; k++) {
+        for (int a = 0; a < 3; a++) { dp[k][a] = 0.0; dl[k][a] = 0.0; }
+        links[k] = 0;
+    }
     for (int z = 0; z < p->nz; z++) {
-        const double *v = pv + (int64_t)z * 9;
-        for (int a = 0; a < 3; a++) { dp[a] += v[a]; dl[a] += v[3 + a]; }
-        dMbb[0] += v[6];
-        dMbb[1] += v[7];
-        links += (int64_t)v[8];
+        const double *v = pv + (int64_t)z * NV;
+        for (int k = 0; k < K; k++) {
+            for (int a = 0; a < 3; a++) { dp[k][a] += v[7 * k + a]; dl[k][a] += v[7 * k + 3 + a]; }
+            links[k] += (int64_t)v[7 * k + 6];
+        }
+        dMbb[0] += v[7 * K];
+        dMbb[1] += v[7 * K + 1];
     }
     free(pv);
-    return links;
 }
 
 /* ------------------------------------------------------------ one step */
 static void one_step(orc_sim *s) {
     int64_t N = s->N;
     const orc_params *p = &s->p;
-    orc_particle *P = &s->P;
+    const int K = s->K;
 
     moments(s);                 /* 1 */
     virtual_densities(s);       /* 2 */
-    double Fv[3], Tv[3];
+    double Fv[ORC_MAX_EXTRA + 1][3], Tv[ORC_MAX_EXTRA + 1][3];
     forces_impl(s, s->F, Fv, Tv); /* 3 */
     collide(s);                 /* 4-6 */
 
     /* 7: streaming with half-way bounce-back on walls and moving-wall
      * bounce-back on particle nodes (momentum exchange on each link)     */
-    double dp[3], dl[3], dMbb[2];
-    int64_t links = stream_bounce(s, dp, dl, dMbb);
+    double dp[ORC_MAX_EXTRA + 1][3], dl[ORC_MAX_EXTRA + 1][3], dMbb[2];
+    int64_t links[ORC_MAX_EXTRA + 1];
+    stream_bounce(s, dp, dl, dMbb, links);
 
-    /* 8: leap-frog Newton-Euler update of the sphere */
-    double af[3], Fext[3];
+    /* 8: leap-frog Newton-Euler update of each sphere */
+    double af[3], Fext[ORC_MAX_EXTRA + 1][3];
     driving(s, af, Fext);
-    if (p->radius > 0.0) {
-        double mp = p->rho_p * particle_volume(s);
-        double Ip = 0.4 * mp * p->radius * p->radius;
+    int n3[3] = {p->nx, p->ny, p->nz};
+    for (int k = 0; k < K; k++) {
+        orc_particle *P = &s->P[k];
+        double mp = s->rhopk[k] * sphere_volume(s, k);
+        double Ip = 0.4 * mp * s->Rk[k] * s->Rk[k];
         for (int a = 0; a < 3; a++) {
-            P->F[a] = dp[a] - Fv[a] + Fext[a] + P->Pev[a];
-            P->T[a] = dl[a] - Tv[a] + P->Lev[a];
+            P->F[a] = dp[k][a] - Fv[k][a] + Fext[k][a] + P->Pev[a];
+            P->T[a] = dl[k][a] - Tv[k][a] + P->Lev[a];
             if (!p->fixed_velocity) {
                 P->U[a] += P->F[a] / mp;
                 P->W[a] += P->T[a] / Ip;
             }
         }
-        int n3[3] = {p->nx, p->ny, p->nz};
         for (int a = 0; a < 3; a++) {
             P->X[a] += P->U[a];
             if (!(p->walls & (1u << a))) {
@@ -646,24 +708,28 @@ static void one_step(orc_sim *s) {
             P->Pev[a] = 0.0;
             P->Lev[a] = 0.0;
         }
+        P->n_links = links[k];
     }
-    P->n_links = links;
+    if (K == 0) s->P[0].n_links = 0;
     series_push(s);
 
-    /* 9: cover / uncover against the particle nodes at X^{n+1} */
+    /* 9: cover / uncover against the particle nodes at X^{n+1}; a covered
+     * node's momentum goes to the sphere that now holds it, an uncovered
+     * node takes the rigid velocity of the sphere that held it           */
     double dMcov[2] = {0, 0}, dMunc[2] = {0, 0};
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
                 int64_t n = node_index(s, x, y, z);
-                s->solid_new[n] = (unsigned char)particle_node(s, x, y, z, P->X);
+                s->solid_new[n] = owner_of(s, x, y, z, s->P);
             }
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++) {
                 int64_t n = node_index(s, x, y, z);
                 if (!s->solid[n] && s->solid_new[n]) { /* covered */
+                    orc_particle *P = &s->P[s->solid_new[n] - 1];
                     double j[3] = {0, 0, 0}, r[3], t[3];
                     for (int l = 0; l < 2; l++) {
                         double rl = 0.0;
@@ -685,6 +751,7 @@ static void one_step(orc_sim *s) {
             for (int x = 0; x < p->nx; x++) {
                 int64_t n = node_index(s, x, y, z);
                 if (!(s->solid[n] && !s->solid_new[n])) continue; /* uncovered only */
+                orc_particle *P = &s->P[s->solid[n] - 1];
                 double rb[2] = {0, 0};
                 int cnt = 0;
                 for (int i = 1; i < Q; i++) {
@@ -725,18 +792,23 @@ static void one_step(orc_sim *s) {
     /* 10: global mass correction over Phi^{n+1} */
     double nf = 0.0;
     for (int64_t n = 0; n < N; n++) nf += s->solid_new[n] ? 0.0 : 1.0;
-    for (int l = 0; l < 2; l++) P->delta[l] = -(dMbb[l] + dMcov[l] + dMunc[l]) / nf;
+    double delta[2];
+    for (int l = 0; l < 2; l++) delta[l] = -(dMbb[l] + dMcov[l] + dMunc[l]) / nf;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         if (s->solid_new[n]) continue;
         for (int l = 0; l < 2; l++)
-            for (int i = 0; i < Q; i++) FI(s->fnew, l, i, n) += s->W[i] * P->delta[l];
+            for (int i = 0; i < Q; i++) FI(s->fnew, l, i, n) += s->W[i] * delta[l];
     }
-    P->n_fluid = nf;
+    for (int k = 0; k < K || k == 0; k++) {
+        s->P[k].delta[0] = delta[0];
+        s->P[k].delta[1] = delta[1];
+        s->P[k].n_fluid = nf;
+        s->P[k].step++;
+    }
 
     double *t = s->f; s->f = s->fnew; s->fnew = t;
     unsigned char *u8 = s->solid; s->solid = s->solid_new; s->solid_new = u8;
-    P->step++;
 }
 
 int orc_set_threads(int32_t n) {
@@ -761,15 +833,31 @@ void orc_set_populations(orc_sim *s, const double *f) {
     memcpy(s->f, f, (size_t)(2 * Q * s->N) * sizeof(double));
 }
 
-void orc_get_particle(const orc_sim *s, orc_particle *out) { *out = s->P; }
+void orc_get_particle(const orc_sim *s, orc_particle *out) { *out = s->P[0]; }
 
-void orc_set_particle(orc_sim *s, const orc_particle *in) {
-    s->P = *in;
+static void reset_solid(orc_sim *s) {
     const orc_params *p = &s->p;
     for (int z = 0; z < p->nz; z++)
         for (int y = 0; y < p->ny; y++)
             for (int x = 0; x < p->nx; x++)
-                s->solid[node_index(s, x, y, z)] = (unsigned char)particle_node(s, x, y, z, s->P.X);
+                s->solid[node_index(s, x, y, z)] = owner_of(s, x, y, z, s->P);
+}
+
+void orc_set_particle(orc_sim *s, const orc_particle *in) {
+    s->P[0] = *in;
+    reset_solid(s);
+}
+
+int32_t orc_n_spheres(const orc_sim *s) { return s->K; }
+
+void orc_get_sphere(const orc_sim *s, int32_t k, orc_particle *out) {
+    *out = s->P[k >= 0 && k < s->K ? k : 0];
+}
+
+void orc_set_sphere(orc_sim *s, int32_t k, const orc_particle *in) {
+    if (k < 0 || k >= s->K) return;
+    s->P[k] = *in;
+    reset_solid(s);
 }
 
 void orc_get_fields(const orc_sim *s, double *rho, double *u) {
@@ -806,8 +894,13 @@ void orc_observables(const orc_sim *s, double mass[2], double mom[3]) {
 }
 
 int64_t orc_u_series(const orc_sim *s, double *u3, int64_t cap) {
+    return orc_u_series_sphere(s, 0, u3, cap);
+}
+
+int64_t orc_u_series_sphere(const orc_sim *s, int32_t k, double *u3, int64_t cap) {
+    if (k < 0 || (k >= s->K && k > 0)) return 0;
     int64_t n = s->series_len < cap ? s->series_len : cap;
-    memcpy(u3, s->series, (size_t)(3 * n) * sizeof(double));
+    memcpy(u3, s->series[k], (size_t)(3 * n) * sizeof(double));
     return s->series_len;
 }
 
@@ -975,7 +1068,7 @@ static void load_snapshot(orc_sim *s, const double *f, const orc_particle *P) {
 
 int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J) {
     const orc_params *p = &s->p;
-    if (nsteps < 1 || p->radius <= 0.0 || p->tau_shear != 1.0 || p->tau_bulk != 1.0 ||
+    if (nsteps < 1 || p->radius <= 0.0 || s->K != 1 || p->tau_shear != 1.0 || p->tau_bulk != 1.0 ||
         p->tau_mom != 1.0 || p->tau_ghost != 1.0)
         return -1;
     int64_t N = s->N;
@@ -1001,12 +1094,12 @@ int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J) {
     double Jsum = 0.0;
     for (int32_t k = 0; k < nsteps; k++) {
         memcpy(snapf + (size_t)k * popn, s->f, popn * sizeof(double));
-        snapP[k] = s->P;
+        snapP[k] = s->P[0];
         one_step(s);
-        Jsum += s->P.U[2];
+        Jsum += s->P[0].U[2];
     }
     memcpy(snapf + (size_t)nsteps * popn, s->f, popn * sizeof(double));
-    snapP[nsteps] = s->P;
+    snapP[nsteps] = s->P[0];
     *J = Jsum / nsteps;
 
     double mp = p->rho_p * particle_volume(s);
@@ -1028,11 +1121,12 @@ int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J) {
         const orc_particle *Pn = &snapP[n], *P1 = &snapP[n + 1];
         moments(s);
         virtual_densities(s);
-        double Fv[3], Tv[3];
+        double Fv[1][3], Tv[1][3];
         forces_impl(s, s->F, Fv, Tv);
         collide(s);
-        double dp[3], dl[3], dMbb[2];
-        stream_bounce(s, dp, dl, dMbb);
+        double dp[1][3], dl[1][3], dMbb[2];
+        int64_t links[1];
+        stream_bounce(s, dp, dl, dMbb, links);
         for (int z = 0; z < p->nz; z++)
             for (int y = 0; y < p->ny; y++)
                 for (int x = 0; x < p->nx; x++)
@@ -1236,7 +1330,7 @@ int orc_adjoint(orc_sim *s, int32_t nsteps, double grad[5], double *J) {
 
         /* 3: forces F_l(x) = sum_i -G rho_l(x) w_i rt_l'(x + c_i) c_i + rho_l(x) a_f;
          * reaction Fv, Tv (about X^n) on links into particle nodes          */
-        double af[3], Fext[3];
+        double af[3], Fext[1][3];
         driving(s, af, Fext);
         double Fvb[3] = {-Fb[0], -Fb[1], -Fb[2]}, Tvb[3] = {-Tb[0], -Tb[1], -Tb[2]};
         memset(A.rtb, 0, (size_t)(2 * N) * sizeof(double));

@@ -20,6 +20,14 @@
 extern "C" {
 #endif
 
+#define ORC_MAX_EXTRA 7  /* spheres beyond the first                        */
+
+/* A further sphere in the same fluid (several particles, Sec. 5 follow-up) */
+typedef struct orc_sphere {
+    double radius, rho_p, wet_drho;
+    double X0[3], U0[3], W0[3];
+} orc_sphere;
+
 typedef struct orc_params {
     int32_t nx, ny, nz;        /* lattice nodes per axis                              */
     uint32_t walls;            /* bit0: x walls, bit1: y walls, bit2: z walls          */
@@ -38,6 +46,8 @@ typedef struct orc_params {
     int32_t fixed_velocity;    /* 1: sphere keeps U0, W0 (prescribed motion)          */
     int32_t init_split;        /* > 0: planes z >= init_split start from the swapped  */
                                /* densities (rho0[1], rho0[0]), the other phase       */
+    int32_t n_extra;           /* further spheres (radius > 0 of the first required)  */
+    orc_sphere extra[ORC_MAX_EXTRA];
 } orc_params;
 
 typedef struct orc_particle {
@@ -66,6 +76,12 @@ void orc_get_populations(const orc_sim *s, double *f);
 void orc_set_populations(orc_sim *s, const double *f);
 void orc_get_particle(const orc_sim *s, orc_particle *out);
 void orc_set_particle(orc_sim *s, const orc_particle *in);
+/* Sphere k (0 = the first) of several: state, and U^{n+1/2} series.  A node
+ * inside several spheres belongs to the first of them.                      */
+int32_t orc_n_spheres(const orc_sim *s);
+void orc_get_sphere(const orc_sim *s, int32_t k, orc_particle *out);
+void orc_set_sphere(orc_sim *s, int32_t k, const orc_particle *in);
+int64_t orc_u_series_sphere(const orc_sim *s, int32_t k, double *u3, int64_t cap);
 /* Per-node fields of the current state: rho[2][N], u[3][N] = v^(H) (solid: 0) */
 void orc_get_fields(const orc_sim *s, double *rho, double *u);
 /* Global observables: mass[2], fluid momentum[3] (sum of raw j over fluid nodes) */
@@ -74,7 +90,7 @@ void orc_observables(const orc_sim *s, double mass[2], double mom[3]);
 int64_t orc_u_series(const orc_sim *s, double *u3, int64_t cap);
 
 /* Adjoint of nsteps steps from the current state (every relaxation time 1,
- * radius > 0): J = (1/nsteps) sum_n U_z^{n+1/2} and
+ * one sphere, radius > 0): J = (1/nsteps) sum_n U_z^{n+1/2} and
  * grad = dJ/d(g_x, g_y, g_z, G, Delta rho).  Runs the steps forward (the
  * simulation ends after them, as orc_step would leave it).  Returns 0, -1 for
  * an unsupported configuration, -2 when memory runs out.                   */

@@ -14,6 +14,14 @@ LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
 Q = 19
 
 
+MAX_EXTRA = 7
+
+
+class OrcSphere(C.Structure):
+    _fields_ = [("radius", C.c_double), ("rho_p", C.c_double), ("wet_drho", C.c_double),
+                ("X0", C.c_double * 3), ("U0", C.c_double * 3), ("W0", C.c_double * 3)]
+
+
 class OrcParams(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls", C.c_uint32),
@@ -24,7 +32,7 @@ class OrcParams(C.Structure):
         ("radius", C.c_double), ("rho_p", C.c_double), ("wet_drho", C.c_double),
         ("X0", C.c_double * 3), ("U0", C.c_double * 3), ("W0", C.c_double * 3),
         ("noise_diffusive", C.c_int32), ("fixed_velocity", C.c_int32),
-        ("init_split", C.c_int32),
+        ("init_split", C.c_int32), ("n_extra", C.c_int32), ("extra", OrcSphere * MAX_EXTRA),
     ]
 
 
@@ -71,6 +79,12 @@ def lib():
         _lib.orc_adjoint.argtypes = [C.c_void_p, C.c_int32, d, d]
         _lib.orc_set_threads.restype = C.c_int
         _lib.orc_set_threads.argtypes = [C.c_int32]
+        _lib.orc_n_spheres.restype = C.c_int32
+        _lib.orc_n_spheres.argtypes = [C.c_void_p]
+        _lib.orc_get_sphere.argtypes = [C.c_void_p, C.c_int32, C.POINTER(OrcParticle)]
+        _lib.orc_set_sphere.argtypes = [C.c_void_p, C.c_int32, C.POINTER(OrcParticle)]
+        _lib.orc_u_series_sphere.restype = C.c_int64
+        _lib.orc_u_series_sphere.argtypes = [C.c_void_p, C.c_int32, d, C.c_int64]
     return _lib
 
 
@@ -88,12 +102,26 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.
 
 
 def make_params(d: dict) -> OrcParams:
+    """Run parameters; d["spheres"] (optional) lists further spheres as dicts
+    with radius, rho_p, wet_drho, X0, U0, W0."""
     q = dict(DEFAULTS)
     q.update(d)
     if q["X0"] is None:
         q["X0"] = ((q["nx"] - 1) / 2.0, (q["ny"] - 1) / 2.0, (q["nz"] - 1) / 2.0)
     p = OrcParams()
+    extra = list(q.get("spheres", []))
+    if len(extra) > MAX_EXTRA:
+        raise ValueError(f"at most {MAX_EXTRA} further spheres")
+    p.n_extra = len(extra)
+    for k, e in enumerate(extra):
+        sp = p.extra[k]
+        sp.radius, sp.rho_p, sp.wet_drho = float(e["radius"]), float(e.get("rho_p", q["rho_p"])), \
+            float(e.get("wet_drho", 0.0))
+        for name in ("X0", "U0", "W0"):
+            setattr(sp, name, (C.c_double * 3)(*[float(x) for x in e.get(name, (0.0, 0.0, 0.0))]))
     for name, ctype in OrcParams._fields_:
+        if name in ("n_extra", "extra"):
+            continue
         v = q[name]
         if hasattr(ctype, "_length_"):
             setattr(p, name, ctype(*[float(x) for x in v]))
@@ -154,6 +182,37 @@ class OracleSim:
             else:
                 setattr(P, k, v)
         lib().orc_set_particle(self._h, C.byref(P))
+
+    def n_spheres(self) -> int:
+        return int(lib().orc_n_spheres(self._h))
+
+    def sphere(self, k: int) -> dict:
+        """State of sphere k (0: the first; the global fields are shared)."""
+        P = OrcParticle()
+        lib().orc_get_sphere(self._h, int(k), C.byref(P))
+        out = {}
+        for name, ctype in OrcParticle._fields_:
+            v = getattr(P, name)
+            out[name] = np.array(list(v)) if hasattr(ctype, "_length_") else v
+        return out
+
+    def set_sphere(self, k: int, d: dict):
+        P = OrcParticle()
+        lib().orc_get_sphere(self._h, int(k), C.byref(P))
+        for key, v in d.items():
+            cur = getattr(P, key)
+            if hasattr(cur, "_length_"):
+                for i, x in enumerate(v):
+                    cur[i] = float(x)
+            else:
+                setattr(P, key, v)
+        lib().orc_set_sphere(self._h, int(k), C.byref(P))
+
+    def sphere_u_series(self, k: int) -> np.ndarray:
+        n = self.particle()["step"]
+        out = np.empty((max(int(n), 1), 3))
+        m = lib().orc_u_series_sphere(self._h, int(k), _dp(out), out.shape[0])
+        return out[:m]
 
     def fields(self):
         rho = np.empty((2, self.nz, self.ny, self.nx))

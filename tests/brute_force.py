@@ -47,28 +47,44 @@ MINV = np.diag(W) @ M.T @ np.diag(1.0 / B)     # f_i = w_i sum_k e_k(c_i) m_k / 
 
 
 class BruteForce:
-    """One replica; state copied from an oracle simulation at step n."""
+    """One replica; state copied from an oracle simulation at step n.  Several
+    spheres: params["spheres"] lists the further ones (radius, rho_p,
+    wet_drho) and `particle` is then the list of all sphere states; a node
+    inside several spheres belongs to the first of them."""
 
     def __init__(self, params, f, particle, normals):
         self.p = dict(params)
         self.nx, self.ny, self.nz = params["nx"], params["ny"], params["nz"]
         self.walled = [bool(params["walls"] & (1 << a)) for a in range(3)]
         self.f = np.array(f, dtype=np.float64)          # [2][19][nz][ny][nx]
-        self.X = np.array(particle["X"], dtype=float)
-        self.U = np.array(particle["U"], dtype=float)
-        self.Wv = np.array(particle["W"], dtype=float)
-        self.Pev = np.array(particle["Pev"], dtype=float)
-        self.Lev = np.array(particle["Lev"], dtype=float)
-        self.step_no = int(particle["step"])
+        states = particle if isinstance(particle, (list, tuple)) else [particle]
+        geo = [dict(radius=params["radius"], rho_p=params["rho_p"], wet_drho=params["wet_drho"])]
+        geo += [dict(radius=e["radius"], rho_p=e.get("rho_p", params["rho_p"]), wet_drho=e.get("wet_drho", 0.0))
+                for e in params.get("spheres", [])]
+        self.sph = []
+        for g, st in zip(geo, states):
+            R = g["radius"]
+            Vp = 4.0 / 3.0 * np.pi * R ** 3
+            mp = g["rho_p"] * Vp
+            self.sph.append(dict(R=R, rho_p=g["rho_p"], drho=g["wet_drho"], Vp=Vp, mp=mp, Ip=0.4 * mp * R * R,
+                                 X=np.array(st["X"], dtype=float), U=np.array(st["U"], dtype=float),
+                                 W=np.array(st["W"], dtype=float), Pev=np.array(st["Pev"], dtype=float),
+                                 Lev=np.array(st["Lev"], dtype=float), F=np.zeros(3), T=np.zeros(3),
+                                 n_cov=0, n_unc=0))
+        self.step_no = int(states[0]["step"])
         self.normals = normals                           # (node, step) -> 36 standard normals
-        self.n_cov = self.n_unc = 0
-        R = params["radius"]
-        self.Vp = 4.0 / 3.0 * np.pi * R ** 3
-        self.mp = params["rho_p"] * self.Vp
-        self.Ip = 0.4 * self.mp * R * R
-        self.solid = self._solid(self.X)
+        self.owner = self._owner([s["X"] for s in self.sph])
         # initial fluid mass (balanced driving divides the external force by it)
         self.M0 = params["M0"]
+
+    # sphere 0, as the single-sphere form names it
+    X = property(lambda self: self.sph[0]["X"])
+    U = property(lambda self: self.sph[0]["U"])
+    Wv = property(lambda self: self.sph[0]["W"])
+    F = property(lambda self: self.sph[0]["F"])
+    T = property(lambda self: self.sph[0]["T"])
+    n_cov = property(lambda self: self.sph[0]["n_cov"])
+    n_unc = property(lambda self: self.sph[0]["n_unc"])
 
     # ------------------------------------------------------------ geometry
     def _sep(self, d, a):
@@ -83,19 +99,22 @@ class BruteForce:
     def _r(self, pos, X):
         return np.array([self._sep(pos[a] - X[a], a) for a in range(3)])
 
-    def _solid(self, X):
-        R2 = self.p["radius"] ** 2
-        s = np.zeros((self.nz, self.ny, self.nx), dtype=bool)
+    def _owner(self, Xs):
+        """-1 for fluid nodes, else the first sphere containing the node."""
+        own = np.full((self.nz, self.ny, self.nx), -1, dtype=np.int64)
         for z in range(self.nz):
             for y in range(self.ny):
                 for x in range(self.nx):
-                    dx = self._sep(x - X[0], 0)
-                    dy = self._sep(y - X[1], 1)
-                    dz = self._sep(z - X[2], 2)
-                    d2 = dx * dx + dy * dy
-                    d2 = d2 + dz * dz
-                    s[z, y, x] = d2 < R2
-        return s
+                    for k, X in enumerate(Xs):
+                        dx = self._sep(x - X[0], 0)
+                        dy = self._sep(y - X[1], 1)
+                        dz = self._sep(z - X[2], 2)
+                        d2 = dx * dx + dy * dy
+                        d2 = d2 + dz * dz
+                        if d2 < self.sph[k]["R"] ** 2:
+                            own[z, y, x] = k
+                            break
+        return own
 
     def _nb(self, x, y, z, i):
         """(neighbour, crossed_wall): x + c_i wrapped on periodic axes."""
@@ -120,15 +139,19 @@ class BruteForce:
     # ---------------------------------------------------------------- step
     def step(self):
         p = self.p
-        f, solid = self.f, self.solid
-        G, kT, dr = p["G"], p["kT"], p["wet_drho"]
+        f, owner = self.f, self.owner
+        solid = owner >= 0
+        K = len(self.sph)
+        G, kT = p["G"], p["kT"]
         rho = f.sum(axis=1) * ~solid                         # [2][nz][ny][nx]
         jm = np.einsum("lizyx,ia->lazyx", f, C.astype(float)) * ~solid
-        # wetting layer: particle nodes see the mean of their fluid neighbours +- Delta rho
+        # wetting layer: particle nodes see the mean of their fluid neighbours
+        # +- the wetting offset of the sphere holding them
         rt = rho.copy()
         for x, y, z in self._nodes():
             if not solid[z, y, x]:
                 continue
+            dr = self.sph[owner[z, y, x]]["drho"]
             acc, cnt = np.zeros(2), 0
             for i in range(1, Q):
                 (qx, qy, qz), crossed = self._nb(x, y, z, i)
@@ -137,17 +160,18 @@ class BruteForce:
                 acc += rho[:, qz, qy, qx]
                 cnt += 1
             rt[:, z, y, x] = (acc / cnt + np.array([dr, -dr])) if cnt else 0.0
-        # external force on the sphere (Sec. 3 eq. fp) and the fluid's acceleration
+        # external force on each sphere (Sec. 3 eq. fp) and the fluid's acceleration
         g = np.array(p["g"], dtype=float)
         rho_tot0 = p["rho0"][0] + p["rho0"][1]
         if p["force_mode"] == 1:
-            af, Fext = g.copy(), self.Vp * p["rho_p"] * g
+            af = g.copy()
+            Fext = [s["Vp"] * s["rho_p"] * g for s in self.sph]
         else:
-            Fext = self.Vp * (p["rho_p"] - rho_tot0) * g
-            af = -Fext / self.M0
-        # Shan-Chen forces and their reaction on the sphere
+            Fext = [s["Vp"] * (s["rho_p"] - rho_tot0) * g for s in self.sph]
+            af = -sum(Fext) / self.M0
+        # Shan-Chen forces and their reaction on the spheres
         F = np.zeros((2, 3, self.nz, self.ny, self.nx))
-        Fv, Tv = np.zeros(3), np.zeros(3)
+        Fv, Tv = np.zeros((K, 3)), np.zeros((K, 3))
         for x, y, z in self._nodes():
             if solid[z, y, x]:
                 continue
@@ -159,9 +183,10 @@ class BruteForce:
                     F[l, :, z, y, x] += fl
                     link += fl
                 if not crossed and solid[qz, qy, qx]:
-                    r = self._r(np.array([x, y, z]) + 0.5 * C[i], self.X)
-                    Fv += link
-                    Tv += np.cross(r, link)
+                    k = owner[qz, qy, qx]
+                    r = self._r(np.array([x, y, z]) + 0.5 * C[i], self.sph[k]["X"])
+                    Fv[k] += link
+                    Tv[k] += np.cross(r, link)
             for l in range(2):
                 F[l, :, z, y, x] += rho[l, z, y, x] * af
         # collision in population space through the dense mode matrix
@@ -200,9 +225,9 @@ class BruteForce:
                     for k in range(4, Q):
                         ms[k] += np.sqrt(mu * rp * B[k] * (1 - gam[k] ** 2)) * zz[16 * l + k - 4]
                 fpost[l, :, z, y, x] = MINV @ ms
-        # streaming, half-way bounce-back on walls, moving-wall bounce-back on the sphere
+        # streaming, half-way bounce-back on walls, moving-wall bounce-back on the spheres
         fnew = np.zeros_like(f)
-        dp, dl, dMbb = np.zeros(3), np.zeros(3), np.zeros(2)
+        dp, dl, dMbb = np.zeros((K, 3)), np.zeros((K, 3)), np.zeros(2)
         for x, y, z in self._nodes():
             if solid[z, y, x]:
                 continue
@@ -212,49 +237,57 @@ class BruteForce:
                 if crossed:
                     fnew[:, OPP[i], z, y, x] = fpost[:, i, z, y, x]
                 elif solid[qz, qy, qx]:
-                    r = self._r(np.array([x, y, z]) + 0.5 * C[i], self.X)
-                    ub = self.U + np.cross(self.Wv, r)
+                    k = owner[qz, qy, qx]
+                    sp = self.sph[k]
+                    r = self._r(np.array([x, y, z]) + 0.5 * C[i], sp["X"])
+                    ub = sp["U"] + np.cross(sp["W"], r)
                     lp = np.zeros(3)
                     for l in range(2):
                         corr = 6 * W[i] * rho[l, z, y, x] * (C[i] @ ub)
                         fnew[l, OPP[i], z, y, x] = fpost[l, i, z, y, x] - corr
                         lp += (2 * fpost[l, i, z, y, x] - corr) * C[i]
                         dMbb[l] -= corr
-                    dp += lp
-                    dl += np.cross(r, lp)
+                    dp[k] += lp
+                    dl[k] += np.cross(r, lp)
                 else:
                     fnew[:, i, qz, qy, qx] = fpost[:, i, z, y, x]
-        # leap-frog Newton-Euler
-        Ftot = dp - Fv + Fext + self.Pev
-        Ttot = dl - Tv + self.Lev
-        if not p["fixed_velocity"]:
-            self.U = self.U + Ftot / self.mp
-            self.Wv = self.Wv + Ttot / self.Ip
+        # leap-frog Newton-Euler of each sphere
         n3 = (self.nx, self.ny, self.nz)
-        Xn = self.X + self.U
-        for a in range(3):
-            if not self.walled[a]:
-                if Xn[a] >= n3[a]:
-                    Xn[a] -= n3[a]
-                elif Xn[a] < 0:
-                    Xn[a] += n3[a]
-        self.X = Xn
-        self.F, self.T = Ftot, Ttot
-        self.Pev, self.Lev = np.zeros(3), np.zeros(3)
-        # cover / uncover against the particle nodes at X^{n+1}
-        snew = self._solid(self.X)
+        for k, sp in enumerate(self.sph):
+            Ftot = dp[k] - Fv[k] + Fext[k] + sp["Pev"]
+            Ttot = dl[k] - Tv[k] + sp["Lev"]
+            if not p["fixed_velocity"]:
+                sp["U"] = sp["U"] + Ftot / sp["mp"]
+                sp["W"] = sp["W"] + Ttot / sp["Ip"]
+            Xn = sp["X"] + sp["U"]
+            for a in range(3):
+                if not self.walled[a]:
+                    if Xn[a] >= n3[a]:
+                        Xn[a] -= n3[a]
+                    elif Xn[a] < 0:
+                        Xn[a] += n3[a]
+            sp["X"] = Xn
+            sp["F"], sp["T"] = Ftot, Ttot
+            sp["Pev"], sp["Lev"] = np.zeros(3), np.zeros(3)
+        # cover / uncover against the particle nodes at X^{n+1}: a covered node
+        # feeds the sphere now holding it, an uncovered one takes the rigid
+        # velocity of the sphere that held it
+        onew = self._owner([sp["X"] for sp in self.sph])
+        snew = onew >= 0
         dMcov, dMunc = np.zeros(2), np.zeros(2)
         for x, y, z in self._nodes():
             if not solid[z, y, x] and snew[z, y, x]:
+                sp = self.sph[onew[z, y, x]]
                 j = np.einsum("li,ia->a", fnew[:, :, z, y, x], C.astype(float))
-                r = self._r(np.array([x, y, z], dtype=float), self.X)
-                self.Pev += j
-                self.Lev += np.cross(r, j)
+                r = self._r(np.array([x, y, z], dtype=float), sp["X"])
+                sp["Pev"] = sp["Pev"] + j
+                sp["Lev"] = sp["Lev"] + np.cross(r, j)
                 dMcov -= fnew[:, :, z, y, x].sum(axis=1)
-                self.n_cov += 1
+                sp["n_cov"] += 1
         for x, y, z in self._nodes():
             if not (solid[z, y, x] and not snew[z, y, x]):
                 continue
+            sp = self.sph[owner[z, y, x]]
             acc, cnt = np.zeros(2), 0
             for i in range(1, Q):
                 (qx, qy, qz), crossed = self._nb(x, y, z, i)
@@ -263,20 +296,20 @@ class BruteForce:
                 acc += fnew[:, :, qz, qy, qx].sum(axis=1)
                 cnt += 1
             rbar = acc / cnt if cnt else np.array(p["rho0"], dtype=float)
-            r = self._r(np.array([x, y, z], dtype=float), self.X)
-            u = self.U + np.cross(self.Wv, r)
+            r = self._r(np.array([x, y, z], dtype=float), sp["X"])
+            u = sp["U"] + np.cross(sp["W"], r)
             cu = C @ u
             for l in range(2):
                 fnew[l, :, z, y, x] = W * rbar[l] * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (u @ u))
             dMunc += rbar
             mom = rbar.sum() * u
-            self.Pev -= mom
-            self.Lev -= np.cross(r, mom)
-            self.n_unc += 1
+            sp["Pev"] = sp["Pev"] - mom
+            sp["Lev"] = sp["Lev"] - np.cross(r, mom)
+            sp["n_unc"] += 1
         fnew[:, :, snew] = 0.0
         # global mass correction over the fluid nodes of step n+1
         nf = float((~snew).sum())
         delta = -(dMbb + dMcov + dMunc) / nf
         fnew += (W[None, :, None, None, None] * delta[:, None, None, None, None]) * (~snew)[None, None]
-        self.f, self.solid = fnew, snew
+        self.f, self.owner = fnew, onew
         self.step_no += 1

@@ -563,7 +563,7 @@ _PLANTS = {
     # Guo term of mode 5 with the wrong sign of u.F
     "guo": ("phi[5] = 2.0 * (3.0 * u[0] * Fl[0] - uF);", "phi[5] = 2.0 * (3.0 * u[0] * Fl[0] + uF);"),
     # wetting offset added to component B instead of subtracted
-    "wetting": ("s->rt[N + n] = sum[1] / cnt - p->wet_drho;", "s->rt[N + n] = sum[1] / cnt + p->wet_drho;"),
+    "wetting": ("s->rt[N + n] = sum[1] / cnt - drho;", "s->rt[N + n] = sum[1] / cnt + drho;"),
     # link torque with the operands of the cross product swapped
     "torque": ("                        cross(r, lp, t);", "                        cross(lp, r, t);"),
 }
