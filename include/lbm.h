@@ -37,7 +37,8 @@
  * work.  lbm_last_error() gives a message.  A step that produces a
  * non-finite or negative density, or a sphere that leaves its channel, sets
  * a sticky flag: the state queries then return LBM_EUNSTABLE (after filling
- * their outputs) until lbm_restore().
+ * their outputs) until lbm_restore().  Spheres of one fluid whose bounding
+ * boxes meet set another (LBM_ECONTACT, see "Several spheres").
  *
  * Streams.  All device work is enqueued on the hip_stream given to
  * lbm_init (NULL = the default stream).  lbm_step is asynchronous; the query
@@ -60,7 +61,8 @@ enum {
     LBM_ENOMEM = -2,    /* workspace too small or misaligned            */
     LBM_EDEVICE = -3,   /* HIP runtime error                            */
     LBM_EUNSTABLE = -4, /* the run went unstable (sticky)               */
-    LBM_ESTATE = -5     /* call not valid in the current context state  */
+    LBM_ESTATE = -5,    /* call not valid in the current context state  */
+    LBM_ECONTACT = -6   /* spheres in one fluid came into contact (sticky) */
 };
 
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };
@@ -98,7 +100,33 @@ typedef struct lbm_params {
                                /* flat A|B interface at z = k - 1/2.  LBM_FP16 storage is  */
                                /* relative to rho0, so it holds the swapped phase to about */
                                /* 1e-3 of rho0[0] / rho0[1] only: use FP32 or FP64 there   */
+    int32_t shared_fluid;      /* 0: this entry starts a replica (its own fluid); 1: one   */
+                               /* more sphere in the fluid of the entry before it (several */
+                               /* spheres per fluid, the multi-particle follow-up of Sec. 5)*/
+                               /* -- see "Several spheres" below                            */
 } lbm_params;
+
+/* Several spheres.  The parameter array passed to lbm_init is a list of
+ * entries.  An entry with shared_fluid = 0 starts a replica: its fluid, and
+ * its sphere when radius > 0.  Each following entry with shared_fluid = 1
+ * adds one sphere to that fluid, up to 16 spheres per fluid: its radius,
+ * rho_p, wet_drho, X0, U0 and W0 are its own, and every other field is
+ * taken from the replica's first entry.  All spheres of a fluid need
+ * radius > 0.  Every sphere keeps its own moving-wall links, wetting layer,
+ * cover / uncover events and Newton-Euler step (Sec. 2, applied to each).
+ * The mass correction is global: the fluxes of all the spheres are summed,
+ * then spread over the fluid nodes that are in no sphere.  Under balanced
+ * driving (force_mode 0) the fluid carries minus the sum of the spheres'
+ * external forces.  The replica argument of the query calls is an entry
+ * index.  lbm_particle_state and lbm_u_series report that entry's sphere;
+ * lbm_populations, lbm_fields and lbm_observables report the shared fluid
+ * for every entry of a replica.  Each sphere's work covers its bounding box
+ * of edge 2 ceil(R) + 6, and the boxes of one fluid must be disjoint:
+ * lbm_init rejects spheres whose initial boxes share a node (LBM_EINVAL),
+ * and a step that brings two boxes together sets a sticky flag, after which
+ * the state queries return LBM_ECONTACT.  Boxes meet when the gap between
+ * two spheres falls below 4 to 8 lattice units along an axis (the exact
+ * value depends on the radii and on the centres' fractional parts). */
 
 /* Sphere state after the last completed step n. */
 typedef struct lbm_particle {

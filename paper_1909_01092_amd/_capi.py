@@ -10,7 +10,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE, LBM_ECONTACT = \
+    0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2}
 
 
@@ -24,7 +25,7 @@ class LbmParams(C.Structure):
         ("radius", C.c_double), ("rho_p", C.c_double), ("wet_drho", C.c_double),
         ("X0", C.c_double * 3), ("U0", C.c_double * 3), ("W0", C.c_double * 3),
         ("noise_diffusive", C.c_int32), ("fixed_velocity", C.c_int32),
-        ("series_cap", C.c_int32), ("init_split", C.c_int32),
+        ("series_cap", C.c_int32), ("init_split", C.c_int32), ("shared_fluid", C.c_int32),
     ]
 
 

@@ -49,6 +49,19 @@ int bbox_edge(const lbm_params &p) {
     return has_sphere(p) ? 2 * (int)std::ceil(p.radius) + 6 : 0;
 }
 
+// Entries grouped into fluids: an entry with shared_fluid = 1 is one more
+// sphere in the fluid of the entry before it.  q holds the entries with the
+// fluid fields of each group's primary (the sphere fields stay their own).
+struct Groups {
+    std::vector<lbm_params> q;
+    std::vector<int> prim, nsph;
+};
+
+// initial bounding-box origin of a sphere (as the device forms it)
+void init_org(const lbm_params &q, int32_t org[3]) {
+    for (int a = 0; a < 3; a++) org[a] = (int32_t)std::floor(q.X0[a] - q.radius) - 2;
+}
+
 struct Layout {
     size_t tables, desc, state, pop[2], part1, part3, raw, vrho, rho_n, pmask, series, aux, total;
     std::vector<int64_t> pop_off, bbox_off, part3_off, series_off, init_wg;
@@ -57,18 +70,27 @@ struct Layout {
     size_t aux_doubles = 0;
 };
 
-Layout plan(const lbm_params *p, int n, int prec) {
+// populations, fluid nodes and initial-state workgroups per group (its
+// primary); boxes, partials and U series per entry
+Layout plan(const Groups &G, int prec) {
     Layout L;
+    const lbm_params *p = G.q.data();
+    const int n = (int)G.q.size();
     const size_t es = elem_size(prec);
     L.pop_off.resize(n); L.bbox_off.resize(n); L.part3_off.resize(n);
     L.series_off.resize(n); L.S.resize(n); L.k3_count.resize(n); L.init_wg.resize(n);
     size_t max_cols = 0;
     for (int r = 0; r < n; r++) {
+        const bool primary = G.prim[r] == r;
         const int64_t N = (int64_t)p[r].nx * p[r].ny * p[r].nz;
         const int64_t NP = (int64_t)(p[r].nx + 2) * (p[r].ny + 2) * (p[r].nz + 2);
-        L.pop_off[r] = 38 * L.NPtot;
-        L.NPtot += NP;
-        L.Ntot += N;
+        if (primary) {
+            L.pop_off[r] = 38 * L.NPtot;
+            L.NPtot += NP;
+            L.Ntot += N;
+        } else {
+            L.pop_off[r] = L.pop_off[G.prim[r]];
+        }
         L.S[r] = bbox_edge(p[r]);
         const int64_t S3 = (int64_t)L.S[r] * L.S[r] * L.S[r];
         L.bbox_off[r] = L.S3tot;
@@ -78,7 +100,7 @@ Layout plan(const lbm_params *p, int n, int prec) {
         L.part3_tot += (int64_t)L.k3_count[r] * PART;
         L.series_off[r] = L.series_tot;
         L.series_tot += 3 * (int64_t)p[r].series_cap;
-        L.init_wg[r] = (N + INIT_BLOCK - 1) / INIT_BLOCK;
+        L.init_wg[r] = primary ? (N + INIT_BLOCK - 1) / INIT_BLOCK : 0;
         L.init_tot += L.init_wg[r];
         max_cols = std::max(max_cols, (size_t)8 * p[r].nx * p[r].ny);
     }
@@ -111,10 +133,41 @@ std::string fmt(const char *f, ...) {
     return buf;
 }
 
-std::string validate(const lbm_params *p, int n, int prec) {
-    if (!p) return "params is NULL";
+std::string validate(const lbm_params *praw, int n, int prec, Groups &G) {
+    if (!praw) return "params is NULL";
     if (n < 1) return "n_replicas must be >= 1";
     if (prec < LBM_FP64 || prec > LBM_FP16) return "precision must be LBM_FP64, LBM_FP32 or LBM_FP16";
+    G.q.assign(praw, praw + n);
+    G.prim.assign(n, 0);
+    G.nsph.assign(n, 1);
+    for (int r = 0; r < n; r++) {
+        const int32_t sf = praw[r].shared_fluid;
+        if (sf != 0 && sf != 1) return fmt("entry %d: shared_fluid must be 0 or 1", r);
+        if (sf == 0) {
+            G.prim[r] = r;
+            continue;
+        }
+        if (r == 0) return "entry 0: shared_fluid needs an entry before it";
+        const int pr = G.prim[r - 1];
+        G.prim[r] = pr;
+        if (!has_sphere(praw[pr]) || !has_sphere(praw[r]))
+            return fmt("entry %d: spheres sharing a fluid need radius > 0 (and so does entry %d)", r, pr);
+        if (r - pr + 1 > MAX_GROUP) return fmt("entry %d: more than %d spheres in one fluid", r, MAX_GROUP);
+        lbm_params q = praw[pr];  // the fluid is the primary's
+        q.radius = praw[r].radius;
+        q.rho_p = praw[r].rho_p;
+        q.wet_drho = praw[r].wet_drho;
+        for (int a = 0; a < 3; a++) {
+            q.X0[a] = praw[r].X0[a];
+            q.U0[a] = praw[r].U0[a];
+            q.W0[a] = praw[r].W0[a];
+        }
+        q.shared_fluid = 1;
+        G.q[r] = q;
+    }
+    for (int r = 0; r < n; r++) G.nsph[G.prim[r]] = r - G.prim[r] + 1;
+    for (int r = 0; r < n; r++) G.nsph[r] = G.nsph[G.prim[r]];
+    const lbm_params *p = G.q.data();
     for (int r = 0; r < n; r++) {
         const lbm_params &q = p[r];
         const int nn[3] = {q.nx, q.ny, q.nz};
@@ -159,13 +212,27 @@ std::string validate(const lbm_params *p, int n, int prec) {
             }
         }
     }
+    // spheres in one fluid start with disjoint bounding boxes
+    for (int r = 0; r < n; r++) {
+        if (G.prim[r] == r) continue;
+        const int32_t n3[3] = {p[r].nx, p[r].ny, p[r].nz};
+        int32_t oa[3];
+        init_org(p[r], oa);
+        for (int e = G.prim[r]; e < r; e++) {
+            int32_t ob[3];
+            init_org(p[e], ob);
+            if (boxes_overlap(oa, bbox_edge(p[r]), ob, bbox_edge(p[e]), n3, p[r].walls))
+                return fmt("entries %d and %d: the spheres' bounding boxes (edge 2 ceil(R) + 6) overlap", e, r);
+        }
+    }
     return "";
 }
 
 }  // namespace
 
 struct lbm_ctx {
-    std::vector<lbm_params> p;
+    std::vector<lbm_params> p;     // entries, fluid fields resolved to each group's primary
+    std::vector<int> prim, nsph;   // group primary and group size of each entry
     int nrep = 0, prec = 0;
     size_t es = 0;
     char *ws = nullptr;
@@ -180,6 +247,7 @@ struct lbm_ctx {
     size_t lds = 0;
     int cur = 0;
     int tau1 = 0;
+    int groups = 0;           // some fluid holds several spheres
     int graph_steps = 0, graph_parity = -1;
     hipGraphExec_t gexec = nullptr;
     bool timing = false;
@@ -254,15 +322,22 @@ void build_tiling(lbm_ctx *c) {
         D.nty = (q.ny + D.ty - 1) / D.ty;
         D.cz = std::min(c->cz, q.nz);
         D.nchunk = (q.nz + D.cz - 1) / D.cz;
+        // main-kernel tiles for a group's primary only (an entry with none is
+        // never the last one at or below a workgroup's index)
         D.wg_begin = wg;
         wg_begin[r] = wg;
-        wg += D.nty * D.nchunk;
+        if (c->prim[r] == r) wg += D.nty * D.nchunk;
         D.k3_begin = k3;
         k3_begin[r] = k3;
         D.k3_count = c->L.k3_count[r];
         k3 += D.k3_count;
         init_begin[r] = iw;
         iw += (int)c->L.init_wg[r];
+    }
+    for (int r = 0; r < n; r++) {
+        RepDesc &D = c->desc[r];
+        D.k3_total = 0;
+        for (int e = c->prim[r]; e < c->prim[r] + c->nsph[r]; e++) D.k3_total += c->L.k3_count[e];
     }
     wg_begin[n] = wg;
     k3_begin[n] = k3;
@@ -280,6 +355,7 @@ int auto_zchunk(lbm_ctx *c) {
     for (int cz = 16; cz >= 2; cz /= 2) {
         int64_t wgs = 0;
         for (int r = 0; r < c->nrep; r++) {
+            if (c->prim[r] != r) continue;
             const lbm_params &q = c->p[r];
             const int ty = tile_rows(c, q);
             wgs += (int64_t)((q.ny + ty - 1) / ty) * ((q.nz + cz - 1) / cz);
@@ -327,6 +403,7 @@ int enqueue_step(lbm_ctx *c, bool timed, const StepScratch &sc) {
     m.vrho = c->d_vrho();
     m.rho_n = sc.rho_n;
     m.tau1 = c->tau1;
+    m.groups = c->groups;
     if (timed && c->ev_used + 2 > c->ev.size()) {
         for (int k = 0; k < 256; k++) {
             hipEvent_t e;
@@ -376,6 +453,14 @@ int enqueue_step(lbm_ctx *c, bool timed, const StepScratch &sc) {
     return LBM_OK;
 }
 
+// status of a replica's sticky flags
+int flag_status(lbm_ctx *c, uint32_t flags) {
+    if (flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "run went unstable");
+    if (flags & FLAG_CONTACT)
+        return fail(c, LBM_ECONTACT, "two spheres in one fluid came close enough for their bounding boxes to overlap");
+    return LBM_OK;
+}
+
 int check_rep(lbm_ctx *c, int r) {
     if (!c) return LBM_EINVAL;
     if (r < 0 || r >= c->nrep) return fail(c, LBM_EINVAL, fmt("replica %d out of range", r));
@@ -402,7 +487,7 @@ struct AdjLayout {
 
 int adj_check(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     if (!c) return LBM_EINVAL;
-    if (c->nrep != 1) return fail(c, LBM_EINVAL, "the adjoint takes a single-replica context");
+    if (c->nrep != 1) return fail(c, LBM_EINVAL, "the adjoint takes a single-replica, single-sphere context");
     if (!c->tau1) return fail(c, LBM_EINVAL, "the adjoint needs every relaxation time equal to 1");
     if (!c->desc[0].has_particle) return fail(c, LBM_EINVAL, "the adjoint needs a sphere (radius > 0)");
     if (nsteps < 1) return fail(c, LBM_EINVAL, "nsteps must be >= 1");
@@ -461,22 +546,25 @@ extern "C" {
 #define LBM_API __attribute__((visibility("default")))
 
 LBM_API int lbm_workspace_bytes(const lbm_params *p, int32_t n_replicas, int32_t precision, size_t *bytes) {
-    const std::string v = validate(p, n_replicas, precision);
+    Groups G;
+    const std::string v = validate(p, n_replicas, precision, G);
     if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
     if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
-    *bytes = plan(p, n_replicas, precision).total;
+    *bytes = plan(G, precision).total;
     return LBM_OK;
 }
 
-LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision, void *dev_ws,
+LBM_API int lbm_init(const lbm_params *p_in, int32_t n_replicas, int32_t precision, void *dev_ws,
              size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
-    const std::string v = validate(p, n_replicas, precision);
+    Groups G;
+    const std::string v = validate(p_in, n_replicas, precision, G);
     if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
     if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
         return fail(nullptr, LBM_ENOMEM, "workspace must be a 256-byte aligned device pointer");
-    Layout L = plan(p, n_replicas, precision);
+    const lbm_params *p = G.q.data();
+    Layout L = plan(G, precision);
     if (ws_bytes < L.total)
         return fail(nullptr, LBM_ENOMEM, fmt("workspace of %zu bytes is smaller than the %zu needed",
                                              ws_bytes, L.total));
@@ -493,6 +581,9 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
         return fail(nullptr, LBM_EDEVICE, "hipGetDevice failed");
     }
     c->L = L;
+    c->prim = G.prim;
+    c->nsph = G.nsph;
+    for (int r = 0; r < n_replicas; r++) c->groups = c->groups || G.nsph[r] > 1;
     c->desc.resize(n_replicas);
     c->tau1 = 1;
     std::vector<RepState> st(n_replicas);
@@ -534,6 +625,8 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
         D.key1 = (uint32_t)(q.seed >> 32) ^ (uint32_t)q.replica;
         D.noise_diffusive = q.noise_diffusive;
         D.fixed_velocity = q.fixed_velocity;
+        D.primary = G.prim[r];
+        D.n_sph = G.nsph[r];
         RepState &s = st[r];
         std::memset(&s, 0, sizeof(s));
         for (int a = 0; a < 3; a++) {
@@ -569,23 +662,30 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
         delete c;
         return LBM_EDEVICE;
     }
+    // initial fluid mass per group (its primary's workgroups), external force
+    // per sphere; under balanced driving the fluid carries minus the sum over
+    // the group's spheres, spread over its mass
     int64_t w = 0;
     for (int r = 0; r < n_replicas; r++) {
         const lbm_params &q = p[r];
         RepDesc &D = c->desc[r];
         double M = 0.0;
         for (int64_t k = 0; k < L.init_wg[r]; k++, w++) M += mass[2 * w] + mass[2 * w + 1];
-        D.M0 = M;
+        D.M0 = G.prim[r] == r ? M : c->desc[G.prim[r]].M0;
         const double V = D.has_particle ? 4.0 / 3.0 * M_PI * q.radius * q.radius * q.radius : 0.0;
         const double rho_tot0 = q.rho0[0] + q.rho0[1];
+        for (int a = 0; a < 3; a++)
+            D.Fext[a] = q.force_mode == 1 ? V * q.rho_p * q.g[a] : V * (q.rho_p - rho_tot0) * q.g[a];
+    }
+    for (int r = 0; r < n_replicas; r++) {
+        const lbm_params &q = p[r];
+        RepDesc &D = c->desc[r];
+        const int pr = G.prim[r];
         for (int a = 0; a < 3; a++) {
-            if (q.force_mode == 1) {
-                D.af[a] = q.g[a];
-                D.Fext[a] = V * q.rho_p * q.g[a];
-            } else {
-                D.Fext[a] = V * (q.rho_p - rho_tot0) * q.g[a];
-                D.af[a] = M > 0.0 ? -D.Fext[a] / M : 0.0;
-            }
+            double tot = 0.0;
+            for (int e = pr; e < pr + G.nsph[r]; e++) tot += c->desc[e].Fext[a];
+            if (q.force_mode == 1) D.af[a] = q.g[a];
+            else D.af[a] = D.M0 > 0.0 ? -tot / D.M0 : 0.0;
         }
     }
     for (int r = 0; r < n_replicas; r++) {
@@ -599,6 +699,32 @@ LBM_API int lbm_init(const lbm_params *p, int32_t n_replicas, int32_t precision,
     }
     rc = upload_desc(c);
     if (rc != LBM_OK) { g_init_error = c->err; delete c; return rc; }
+    // fluid nodes of a group: every sphere's initial layer counted its own
+    // particle nodes only
+    bool groups = false;
+    for (int r = 0; r < n_replicas; r++) groups = groups || G.nsph[r] > 1;
+    if (groups) {
+        e = hipMemcpyAsync(st.data(), c->d_state(), sizeof(RepState) * n_replicas, hipMemcpyDeviceToHost,
+                           c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) {
+            for (int r = 0; r < n_replicas; r++) {
+                if (G.prim[r] != r || G.nsph[r] == 1) continue;
+                const double N = (double)c->desc[r].N;
+                double solid = 0.0;
+                for (int k = r; k < r + G.nsph[r]; k++) solid += N - st[k].n_fluid;
+                for (int k = r; k < r + G.nsph[r]; k++) st[k].n_fluid = N - solid;
+            }
+            e = hipMemcpyAsync(c->d_state(), st.data(), sizeof(RepState) * n_replicas, hipMemcpyHostToDevice,
+                               c->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            g_init_error = fmt("initialisation: %s", hipGetErrorString(e));
+            delete c;
+            return LBM_EDEVICE;
+        }
+    }
     c->cur = 0;
     *out = c;
     return LBM_OK;
@@ -706,8 +832,7 @@ LBM_API int lbm_particle_state(lbm_ctx *c, int32_t replica, lbm_particle *out) {
     out->n_covered = s.n_cov;
     out->n_uncovered = s.n_unc;
     out->n_links = s.n_links;
-    if (s.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "run went unstable");
-    return LBM_OK;
+    return flag_status(c, s.flags);
 }
 
 LBM_API int lbm_populations(lbm_ctx *c, int32_t replica, double *host_f) {
@@ -808,8 +933,7 @@ LBM_API int lbm_observables(lbm_ctx *c, int32_t replica, lbm_obs *o) {
     RepState st;
     rc = read_state(c, replica, &st);
     if (rc != LBM_OK) return rc;
-    if (st.flags & FLAG_UNSTABLE) return fail(c, LBM_EUNSTABLE, "run went unstable");
-    return LBM_OK;
+    return flag_status(c, st.flags);
 }
 
 LBM_API int lbm_u_series(lbm_ctx *c, int32_t replica, double *host_u3, int64_t cap, int64_t *count) {

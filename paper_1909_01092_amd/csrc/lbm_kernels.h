@@ -18,6 +18,7 @@ struct MainArgs {
     const double *vrho;        // wetting-layer densities of step n (bbox)
     double *rho_n;             // densities of step n near the sphere (bbox), written
     int32_t tau1;              // every relaxation time of every replica is 1
+    int32_t groups;            // some fluid holds several spheres
 };
 
 struct LinkArgs {

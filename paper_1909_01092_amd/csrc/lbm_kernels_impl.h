@@ -326,7 +326,9 @@ constexpr bool main_fast_form = sizeof(T) == 4 && TAU1;
 template <typename S, typename T, bool TAU1>
 constexpr bool main_unroll = sizeof(T) == 4 && TAU1;
 
-template <typename S, typename T, int B, bool TAU1>
+// GROUP: fluids may hold several spheres (their boxes are searched too); a
+// separate instantiation, so the single-sphere form keeps its registers.
+template <typename S, typename T, int B, bool TAU1, bool GROUP>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(main_fast_form<S, T, TAU1> ? 4 : 1)))
 void k_main(MainArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -350,6 +352,7 @@ void k_main(MainArgs a) {
     const int pr = (ty + 2) * nx;  // LDS elements per plane and component
 
     const bool hp = D.has_particle;
+    const int nsph = GROUP ? D.n_sph : 1;
     const bool ghost_fill = D.ghost_fill;
     const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
     const T dl[2] = {T(stp->delta[0]), T(stp->delta[1])};
@@ -385,14 +388,36 @@ void k_main(MainArgs a) {
         int b = -1;
         if (hp) b = bbox_index(xx, yy, zz, org, Sx, g);
         if (b < 0 || !(pmask[b] & MASK_SOLID)) {
-            T d[2][Q];
-            pull_node(pcl, pidx(xx, yy, zz, g), d);
-            node_moments(d, s);
-            s.rd[0] += dl[0];
-            s.rd[1] += dl[1];
-            rA = s.rd[0];
-            rB = s.rd[1];
-            return true;
+            // the group's other spheres (their boxes are disjoint from this
+            // one's and from each other, so at most one holds the node)
+            int64_t vi = -1;
+            int vs = 0;
+            if (GROUP && nsph > 1 && b < 0) {
+                for (int e = 1; e < nsph; e++) {
+                    const RepDesc *De = a.desc + r + e;
+                    const int Se = De->S;
+                    const int be = bbox_index(xx, yy, zz, a.state[r + e].org, Se, g);
+                    if (be < 0) continue;
+                    if (a.pmask[De->bbox_off + be] & MASK_SOLID) {
+                        vi = 2 * De->bbox_off + be;
+                        vs = Se * Se * Se;
+                    }
+                    break;
+                }
+            }
+            if (vi < 0) {
+                T d[2][Q];
+                pull_node(pcl, pidx(xx, yy, zz, g), d);
+                node_moments(d, s);
+                s.rd[0] += dl[0];
+                s.rd[1] += dl[1];
+                rA = s.rd[0];
+                rB = s.rd[1];
+                return true;
+            }
+            rA = T(a.vrho[vi] + dld[0] - rho0d[0]);
+            rB = T(a.vrho[vi + vs] + dld[1] - rho0d[1]);
+            return false;
         }
         rA = T(vrho[b] + dld[0] - rho0d[0]);
         rB = T(vrho[S3 + b] + dld[1] - rho0d[1]);
@@ -470,11 +495,22 @@ void k_main(MainArgs a) {
             }
             const T rl[2] = {cf.rho0[0] + rd[0], cf.rho0[1] + rd[1]};
             if (!(rl[0] > T(0)) || !(rl[1] >= T(0))) atomicOr(&stp->flags, FLAG_UNSTABLE);
-            if (hp) {  // densities near the sphere, for the link kernel
+            if (hp) {  // densities near the spheres, for the link kernel
                 const int b = bbox_index(x, y, z, org, Sx, g);
                 if (b >= 0) {
                     rho_n[b] = (double)rl[0];
                     rho_n[S3 + b] = (double)rl[1];
+                } else if (GROUP && nsph > 1) {
+                    for (int e = 1; e < nsph; e++) {
+                        const RepDesc *De = a.desc + r + e;
+                        const int Se = De->S;
+                        const int be = bbox_index(x, y, z, a.state[r + e].org, Se, g);
+                        if (be < 0) continue;
+                        double *rn = a.rho_n + 2 * De->bbox_off;
+                        rn[be] = (double)rl[0];
+                        rn[Se * Se * Se + be] = (double)rl[1];
+                        break;
+                    }
                 }
             }
             T F[2][3];
@@ -982,22 +1018,20 @@ __device__ __forceinline__ void advance_empty(const ParticleArgs &a, const RepDe
     st->step = n + 1;
 }
 
-// Publish step n+1 of one replica from the link sums, the motion and the
-// event totals (one thread): global mass correction
-// delta_l = -(bounce-back flux - covered + uncovered mass)_l / |Phi^{n+1}|,
-// pending event momentum, the U series entry and the stability flags.
-__device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDesc &D, RepState *st,
-                                             const Geo &g, const double (&sum)[15], const Motion &mo,
-                                             const double (&tot)[20]) {
+// Motion of step n+1 of one sphere (one thread): position, velocities,
+// forces, bounding-box origin, pending event momentum, the U series entry and
+// the event counters.  Returns whether the sphere went unstable (|U| >= 1/2,
+// a non-finite force) or reached a wall.
+__device__ __forceinline__ bool publish_motion(const ParticleArgs &a, const RepDesc &D, RepState *st,
+                                               const Geo &g, const double (&sum)[15], const Motion &mo,
+                                               const double (&tot)[20]) {
     const int n3[3] = {g.nx, g.ny, g.nz};
     const bool w3[3] = {g.wx, g.wy, g.wz};
     const double Xold[3] = {st->X[0], st->X[1], st->X[2]};
     const double *utot = tot + 10;
-    const double nf = (double)D.N - tot[9];
     const int64_t n = st->step;
     double *s = a.series + D.series_off + 3 * (n % D.series_cap);
     bool bad = false;
-    for (int l = 0; l < 2; l++) st->delta[l] = -(sum[6 + l] - tot[6 + l] + utot[6 + l]) / nf;
     for (int q = 0; q < 3; q++) {
         st->Xp[q] = Xold[q];
         st->X[q] = mo.Xn[q];
@@ -1013,12 +1047,77 @@ __device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDes
         if (!(fabs(mo.Un[q]) < 0.5) || !isfinite(mo.F[q])) bad = true;
         if (w3[q] && (mo.Xn[q] - D.radius < -0.5 || mo.Xn[q] + D.radius > n3[q] - 0.5)) bad = true;
     }
-    st->n_fluid = nf;
     st->n_cov += (int64_t)tot[8];
     st->n_unc += (int64_t)utot[8];
     st->n_links = (int64_t)sum[14];
+    return bad;
+}
+
+// Publish step n+1 of one replica with a single sphere from the link sums,
+// the motion and the event totals (one thread): global mass correction
+// delta_l = -(bounce-back flux - covered + uncovered mass)_l / |Phi^{n+1}|,
+// then the sphere's motion, the step counter and the stability flag.
+__device__ __forceinline__ void publish_step(const ParticleArgs &a, const RepDesc &D, RepState *st,
+                                             const Geo &g, const double (&sum)[15], const Motion &mo,
+                                             const double (&tot)[20]) {
+    const double *utot = tot + 10;
+    const double nf = (double)D.N - tot[9];
+    for (int l = 0; l < 2; l++) st->delta[l] = -(sum[6 + l] - tot[6 + l] + utot[6 + l]) / nf;
+    const bool bad = publish_motion(a, D, st, g, sum, mo, tot);
+    st->n_fluid = nf;
     if (bad) st->flags |= FLAG_UNSTABLE;
-    st->step = n + 1;
+    st->step = st->step + 1;
+}
+
+// Publish step n+1 of a group of spheres in one fluid (one wave; lane 0
+// writes).  The mass correction is global: the bounce-back, covered and
+// uncovered fluxes and the particle nodes of every sphere are summed before
+// delta_l and |Phi^{n+1}| are formed.  Each sphere then takes its own
+// Newton-Euler step, and every entry of the group receives the shared fields
+// (delta, fluid nodes, step, flags).  Two boxes that now share a node set
+// FLAG_CONTACT on the group.
+__device__ __forceinline__ void publish_group(const ParticleArgs &a, int prim, const Geo &g) {
+    const RepDesc *P = a.desc + prim;
+    const int K = P->n_sph;
+    double dm[2] = {0.0, 0.0}, nsol = 0.0;
+    for (int e = prim; e < prim + K; e++) {
+        const RepDesc *De = a.desc + e;
+        double sum[15], tot[20];
+        sum_partials<15>(a.part1 + De->part3_off, De->k3_count, 0, sum);
+        sum_partials<20>(a.part3 + De->part3_off, De->k3_count, 0, tot);
+        for (int l = 0; l < 2; l++) dm[l] += sum[6 + l] - tot[6 + l] + tot[16 + l];
+        nsol += tot[9];
+    }
+    const double nf = (double)P->N - nsol;
+    const double delta[2] = {-dm[0] / nf, -dm[1] / nf};
+    uint32_t flags = 0u;
+    for (int e = prim; e < prim + K; e++) flags |= a.state[e].flags;
+    const bool lead = (threadIdx.x & 63) == 0;
+    for (int e = prim; e < prim + K; e++) {
+        const RepDesc &De = a.desc[e];
+        RepState *se = a.state + e;
+        double sum[15], tot[20];
+        sum_partials<15>(a.part1 + De.part3_off, De.k3_count, 0, sum);
+        sum_partials<20>(a.part3 + De.part3_off, De.k3_count, 0, tot);
+        Motion mo;
+        newton_euler(De, se, g, sum, mo);
+        if (lead && publish_motion(a, De, se, g, sum, mo, tot)) flags |= FLAG_UNSTABLE;
+    }
+    if (!lead) return;
+    const int32_t n3[3] = {g.nx, g.ny, g.nz};
+    for (int e = prim; e < prim + K; e++)
+        for (int f = e + 1; f < prim + K; f++)
+            if (boxes_overlap(a.state[e].org, a.desc[e].S, a.state[f].org, a.desc[f].S, n3, P->walls))
+                flags |= FLAG_CONTACT;
+    const int64_t step = a.state[prim].step + 1;
+    for (int e = prim; e < prim + K; e++) {
+        RepState *se = a.state + e;
+        se->delta[0] = delta[0];
+        se->delta[1] = delta[1];
+        se->n_fluid = nf;
+        se->flags = flags;
+        se->step = step;
+    }
 }
 
 template <typename S, typename T, int B, bool APART>
@@ -1233,25 +1332,34 @@ __global__ __launch_bounds__(B) void k_particle(ParticleArgs a) {
         for (int k = 0; k < 20; k++) pp[k] = ev[k];
     }
     if constexpr (APART) return;
+    // the counter of the group's primary entry counts the workgroups of every
+    // sphere in the fluid (a single sphere: its own)
+    RepState *sp = a.state + D.primary;
     __threadfence();
     __syncthreads();
-    if (t == 0) last = (atomicAdd(&st->k3_done, 1u) == (unsigned)(D.k3_count - 1));
+    if (t == 0) last = (atomicAdd(&sp->k3_done, 1u) == (unsigned)(D.k3_total - 1));
     __syncthreads();
     if (!last) return;
     __threadfence();
+    // the next launch sees the stores below: kernel boundaries order them
+    if (D.n_sph > 1) {
+        publish_group(a, D.primary, g);
+        if (t == 0) sp->k3_done = 0;
+        return;
+    }
     // last workgroup: event sums (fixed order), then the new state
     double tot[20];
     sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
     if (t != 0) return;
     st->k3_done = 0;
-    // the next launch sees these stores: kernel boundaries order them
     publish_step(a, D, st, g, sum, mo, tot);
 }
 
 // ============================================================== k_finish
-// One wave per replica after k_particle (finish_apart): sums the link and
+// One wave per entry after k_particle (finish_apart): sums the link and
 // event partials in the same fixed order, repeats the Newton-Euler step of
-// k_particle on the same inputs and publishes the state of step n+1.
+// k_particle on the same inputs and publishes the state of step n+1 (a
+// group of spheres in one fluid: its primary's wave publishes them all).
 template <int B>
 __global__ __launch_bounds__(B) void k_finish(ParticleArgs a) {
     const int r = blockIdx.x;
@@ -1263,6 +1371,10 @@ __global__ __launch_bounds__(B) void k_finish(ParticleArgs a) {
         return;
     }
     const Geo g = geo_of(D);
+    if (D.n_sph > 1) {
+        if (D.primary == r) publish_group(a, r, g);
+        return;
+    }
     double sum[15], tot[20];
     sum_partials<15>(a.part1 + D.part3_off, D.k3_count, 0, sum);
     sum_partials<20>(a.part3 + D.part3_off, D.k3_count, 0, tot);
@@ -1281,14 +1393,15 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     const int wg = blockIdx.x;
     const int r = find_rep(a.init_begin, a.nrep, wg);
     const RepDesc &D = a.desc[r];
-    const RepState &st = a.state[r];
     const Geo g = geo_of(D);
     const int64_t n = (int64_t)(wg - a.init_begin[r]) * 256 + threadIdx.x;
     double m[2] = {0.0, 0.0};
     if (n < g.N) {
         const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny);
         const int z = (int)(n / ((int64_t)g.nx * g.ny));
-        const bool solid = D.has_particle && pnode(x, y, z, st.X, D.R2, g);
+        bool solid = false;  // inside any sphere of the replica
+        for (int e = r; e < r + D.n_sph; e++)
+            solid = solid || (a.desc[e].has_particle && pnode(x, y, z, a.state[e].X, a.desc[e].R2, g));
         uint32_t c0 = (uint32_t)n, c1 = 0u, c2 = 0u, c3 = 1u;
         philox4x32_10(c0, c1, c2, c3, D.key0, D.key1);
         const uint32_t w[2] = {c0, c1};
@@ -1314,11 +1427,18 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     }
 }
 
-// solid flag of a box node for the current step
-__device__ __forceinline__ bool solid_now(int x, int y, int z, const RepDesc &D, const RepState &st,
-                                          const uint32_t *pmask, const Geo &g, int &b) {
-    b = D.has_particle ? bbox_index(x, y, z, st.org, D.S, g) : -1;
-    return b >= 0 && (pmask[D.bbox_off + b] & MASK_SOLID);
+// The entry of the group of primary entry prim whose sphere holds node
+// (x, y, z) for the current step (b: its box index), or -1 for a fluid node.
+__device__ __forceinline__ int solid_entry(int x, int y, int z, const RepDesc *desc, const RepState *state,
+                                           const uint32_t *pmask, int prim, const Geo &g, int &b) {
+    for (int e = prim; e < prim + desc[prim].n_sph; e++) {
+        const RepDesc &D = desc[e];
+        if (!D.has_particle) continue;
+        b = bbox_index(x, y, z, state[e].org, D.S, g);
+        if (b >= 0 && (pmask[D.bbox_off + b] & MASK_SOLID)) return e;
+    }
+    b = -1;
+    return -1;
 }
 
 // ============================================================= k_export
@@ -1336,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_export(ExportArgs a) {
     const int x = (int)(k % g.nx), y = (int)((k / g.nx) % g.ny), z = a.z_begin + (int)(k / plane);
     const PullCtx<S, T> pc = pull_ctx<S, T>(a.src, D, g);
     int b;
-    const bool solid = solid_now(x, y, z, D, st, a.pmask, g, b);
+    const bool solid = solid_entry(x, y, z, a.desc, a.state, a.pmask, D.primary, g, b) >= 0;
     T d[2][Q];
     if (!solid) pull_node(pc, pidx(x, y, z, g), d);
     for (int l = 0; l < 2; l++)
@@ -1359,9 +1479,10 @@ __global__ __launch_bounds__(256) void k_fields_a(FieldArgs a) {
     const int z = (int)(n / ((int64_t)g.nx * g.ny));
     double *rt = a.scratch, *jt = a.scratch + 2 * g.N, *sol = a.scratch + 8 * g.N;
     int b;
-    if (solid_now(x, y, z, D, st, a.pmask, g, b)) {
-        const int S3 = D.S * D.S * D.S;
-        const double *vrho = a.vrho + D.bbox_off * 2;
+    const int e = solid_entry(x, y, z, a.desc, a.state, a.pmask, D.primary, g, b);
+    if (e >= 0) {
+        const int S3 = a.desc[e].S * a.desc[e].S * a.desc[e].S;
+        const double *vrho = a.vrho + a.desc[e].bbox_off * 2;
         rt[n] = vrho[b] + st.delta[0];
         rt[g.N + n] = vrho[S3 + b] + st.delta[1];
         for (int q = 0; q < 3; q++) jt[q * g.N + n] = 0.0;
@@ -1383,25 +1504,27 @@ __global__ __launch_bounds__(256) void k_fields_a(FieldArgs a) {
 }
 
 // ============================================================== launchers
-template <typename S, typename T>
-hipError_t launch_main_t(const MainArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-    const bool tau1 = a.tau1 != 0;
+template <typename S, typename T, int B, bool GROUP>
+void launch_main_b(const MainArgs &a, int grid, size_t lds, hipStream_t s) {
+    if (a.tau1) hipLaunchKernelGGL((k_main<S, T, B, true, GROUP>), dim3(grid), dim3(B), lds, s, a);
+    else hipLaunchKernelGGL((k_main<S, T, B, false, GROUP>), dim3(grid), dim3(B), lds, s, a);
+}
+
+template <typename S, typename T, bool GROUP>
+hipError_t launch_main_g(const MainArgs &a, int grid, int block, size_t lds, hipStream_t s) {
     switch (block) {
-    case 256:
-        if (tau1) hipLaunchKernelGGL((k_main<S, T, 256, true>), dim3(grid), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((k_main<S, T, 256, false>), dim3(grid), dim3(256), lds, s, a);
-        break;
-    case 512:
-        if (tau1) hipLaunchKernelGGL((k_main<S, T, 512, true>), dim3(grid), dim3(512), lds, s, a);
-        else hipLaunchKernelGGL((k_main<S, T, 512, false>), dim3(grid), dim3(512), lds, s, a);
-        break;
-    case 1024:
-        if (tau1) hipLaunchKernelGGL((k_main<S, T, 1024, true>), dim3(grid), dim3(1024), lds, s, a);
-        else hipLaunchKernelGGL((k_main<S, T, 1024, false>), dim3(grid), dim3(1024), lds, s, a);
-        break;
+    case 256: launch_main_b<S, T, 256, GROUP>(a, grid, lds, s); break;
+    case 512: launch_main_b<S, T, 512, GROUP>(a, grid, lds, s); break;
+    case 1024: launch_main_b<S, T, 1024, GROUP>(a, grid, lds, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename S, typename T>
+hipError_t launch_main_t(const MainArgs &a, int grid, int block, size_t lds, hipStream_t s) {
+    return a.groups ? launch_main_g<S, T, true>(a, grid, block, lds, s)
+                    : launch_main_g<S, T, false>(a, grid, block, lds, s);
 }
 
 template <typename S, typename T>

@@ -53,6 +53,15 @@ struct RepDesc {
     Coef<float> cf32;
     Coef<double> cf64;
     float G32, af32[3];
+    // Several spheres in one fluid: each sphere is an entry; the first entry
+    // of a group (the primary) owns the populations and the main-kernel
+    // tiles, the others (k = 1 .. n_sph - 1, at primary + k) share them and
+    // carry only their sphere, box and partials.  Every entry of a group
+    // holds the same fluid fields.
+    int32_t primary;         // index of the group's first entry
+    int32_t n_sph;           // entries in the group (1: a single sphere or none)
+    int32_t k3_total;        // particle-kernel workgroups of the whole group
+    int32_t pad_grp;
 };
 
 template <typename T> __host__ __device__ __forceinline__ const Coef<T> &coef_of(const RepDesc &D);
@@ -70,15 +79,39 @@ struct RepState {
     int64_t step, n_cov, n_unc, n_links;
     int32_t org[3];          // origin of the bounding box of X^n
     int32_t pad_org;
-    uint32_t flags;          // bit0 unstable
+    uint32_t flags;          // FLAG_UNSTABLE, FLAG_CONTACT
     uint32_t k3_done;        // particle-kernel completion counter (0 between steps)
     uint32_t pad1[2];
 };
 
 constexpr uint32_t FLAG_UNSTABLE = 1u;
+// two spheres of one group whose bounding boxes share a node (the per-sphere
+// box work then no longer sees every particle node near it)
+constexpr uint32_t FLAG_CONTACT = 2u;
 // Node flag of a bounding-box node for one step: MASK_SOLID = particle node at X^n.
 constexpr uint32_t MASK_SOLID = 1u << 19;
 constexpr int PART = 24;     // doubles per workgroup partial
 constexpr int RAW = 5;       // doubles per box node: rho_A, rho_B, j (post-streaming, step n+1)
+constexpr int MAX_GROUP = 16;  // spheres per fluid
+
+// Whether the boxes of edge Sa at oa and of edge Sb at ob share a node: per
+// axis, half-open intervals on a ring of n nodes (periodic axes, n >= Sa, Sb)
+// or on a line (walled axes); they share a node when they meet on all three.
+__host__ __device__ inline bool boxes_overlap(const int32_t *oa, int Sa, const int32_t *ob, int Sb,
+                                              const int32_t *n3, uint32_t walls) {
+    for (int ax = 0; ax < 3; ax++) {
+        int d1 = ob[ax] - oa[ax], d2 = oa[ax] - ob[ax];
+        bool meet;
+        if (walls & (1u << ax)) {
+            meet = d1 < Sa && d2 < Sb;
+        } else {
+            d1 = ((d1 % n3[ax]) + n3[ax]) % n3[ax];
+            d2 = ((d2 % n3[ax]) + n3[ax]) % n3[ax];
+            meet = d1 < Sa || d2 < Sb;
+        }
+        if (!meet) return false;
+    }
+    return true;
+}
 
 }  // namespace lbm

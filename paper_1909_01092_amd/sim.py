@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _capi
-from .workloads import full
+from .workloads import entries, full
 
 
 def _fill(p: _capi.LbmParams, q: dict):
@@ -25,11 +25,11 @@ def _fill(p: _capi.LbmParams, q: dict):
 
 
 def make_params(replicas) -> C.Array:
-    """ctypes array of lbm_params from one dict or a list of dicts."""
-    if isinstance(replicas, dict):
-        replicas = [replicas]
-    arr = (_capi.LbmParams * len(replicas))()
-    for k, q in enumerate(replicas):
+    """ctypes array of lbm_params entries from one dict or a list of dicts
+    (a dict's "spheres" become entries sharing its fluid)."""
+    ents = entries(replicas)
+    arr = (_capi.LbmParams * len(ents))()
+    for k, q in enumerate(ents):
         _fill(arr[k], full(q))
     return arr
 
@@ -53,7 +53,8 @@ class Simulation:
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Simulation needs a ROCm GPU (torch.cuda.is_available() is False)")
-        self.replicas = [full(q) for q in ([replicas] if isinstance(replicas, dict) else replicas)]
+        # one per lbm_init entry: a replica's extra spheres ("spheres") follow it
+        self.replicas = entries(replicas)
         self.precision = precision
         self.device = torch.device(device)
         self._lib = _capi.lib()
@@ -146,15 +147,18 @@ class Simulation:
 
     # -- queries
     def particle_state(self, replica: int = 0, allow_unstable: bool = False) -> dict:
+        """State of entry `replica`'s sphere.  allow_unstable: return it even
+        when the sticky flags are set ("unstable", "contact" say which)."""
         P = _capi.LbmParticle()
         rc = self._lib.lbm_particle_state(self._ctx, int(replica), C.byref(P))
-        if not (allow_unstable and rc == _capi.LBM_EUNSTABLE):
+        if not (allow_unstable and rc in (_capi.LBM_EUNSTABLE, _capi.LBM_ECONTACT)):
             self._check(rc)
         out = {}
         for name, ctype in _capi.LbmParticle._fields_:
             v = getattr(P, name)
             out[name] = np.array(list(v)) if hasattr(ctype, "_length_") else v
         out["unstable"] = rc == _capi.LBM_EUNSTABLE
+        out["contact"] = rc == _capi.LBM_ECONTACT
         return out
 
     def _dims(self, r):

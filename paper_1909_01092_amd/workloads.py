@@ -10,7 +10,9 @@ DEFAULTS = dict(nx=8, ny=8, nz=8, walls=0, rho0=(0.95, 0.05), init_amp=0.0, G=0.
                 tau_shear=1.0, tau_bulk=1.0, tau_mom=1.0, tau_ghost=1.0, kT=0.0, seed=0,
                 replica=0, g=(0.0, 0.0, 0.0), force_mode=0, radius=0.0, rho_p=2.0,
                 wet_drho=0.0, X0=None, U0=(0.0, 0.0, 0.0), W0=(0.0, 0.0, 0.0),
-                noise_diffusive=1, fixed_velocity=0, series_cap=4096, init_split=0)
+                noise_diffusive=1, fixed_velocity=0, series_cap=4096, init_split=0, shared_fluid=0)
+
+SPHERE_FIELDS = ("radius", "rho_p", "wet_drho", "X0", "U0", "W0")
 
 
 def full(params: dict) -> dict:
@@ -20,6 +22,24 @@ def full(params: dict) -> dict:
     if q["X0"] is None:
         q["X0"] = ((q["nx"] - 1) / 2.0, (q["ny"] - 1) / 2.0, (q["nz"] - 1) / 2.0)
     return q
+
+
+def entries(replicas) -> list:
+    """lbm_init entries of one replica dict or a list of them.  A replica may
+    list further spheres in the same fluid under "spheres" (dicts of
+    SPHERE_FIELDS; missing ones as DEFAULTS): each becomes an entry with
+    shared_fluid = 1 after the replica's own."""
+    if isinstance(replicas, dict):
+        replicas = [replicas]
+    out = []
+    for q in replicas:
+        base = full({k: v for k, v in q.items() if k != "spheres"})
+        out.append(base)
+        for e in q.get("spheres", ()):
+            extra = {k: e.get(k, DEFAULTS[k]) for k in SPHERE_FIELDS if k != "X0"}
+            extra["X0"] = e["X0"]
+            out.append(dict(base, shared_fluid=1, **extra))
+    return out
 
 
 def channel(n: int, nz: int, **kw) -> dict:

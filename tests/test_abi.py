@@ -113,3 +113,53 @@ def test_empty_replica_list_rejected(capi):
     assert L.lbm_workspace_bytes(arr, 0, 1, C.byref(n)) == capi.LBM_EINVAL
     assert L.lbm_workspace_bytes(arr, -3, 1, C.byref(n)) == capi.LBM_EINVAL
     assert b"n_replicas" in L.lbm_last_error(None)
+
+
+def _group(**kw):
+    q = dict(nx=16, ny=16, nz=48, walls=3, radius=2.5, X0=(7.5, 7.5, 8.0),
+             spheres=[dict(radius=2.5, X0=(7.5, 7.5, 30.0))])
+    q.update(kw)
+    return q
+
+
+def test_sphere_group_workspace(capi):
+    """A second sphere in the same fluid adds its box, partials and U series,
+    not a second population block."""
+    one = _bytes(capi, _group(spheres=[]), "fp32")
+    two = _bytes(capi, _group(), "fp32")
+    rep2 = _bytes(capi, [_group(spheres=[]), _group(spheres=[])], "fp32")
+    assert one < two < one + (rep2 - one) // 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(spheres=[dict(radius=2.5, X0=(7.5, 7.5, 17.0))]),    # initial boxes share nodes
+    dict(spheres=[dict(radius=2.5, X0=(7.5, 7.5, 46.0))]),    # ... across the periodic face
+    dict(spheres=[dict(radius=0.0, X0=(7.5, 7.5, 30.0))]),    # a shared entry without a sphere
+    dict(radius=0.0),                                         # a fluid without its own sphere
+    dict(spheres=[dict(radius=2.5, X0=(7.5, 7.5, 30.0), U0=(0.0, 0.0, 0.7))]),
+    dict(spheres=[dict(radius=2.5, X0=(14.0, 7.5, 30.0))]),   # second sphere touches a wall
+])
+def test_invalid_sphere_groups_rejected(capi, bad):
+    with pytest.raises(capi.LbmError) as e:
+        _bytes(capi, _group(**bad), "fp32")
+    assert e.value.code == capi.LBM_EINVAL
+
+
+def test_group_limits_rejected(capi):
+    from paper_1909_01092_amd.sim import make_params
+    L = capi.lib()
+    n = C.c_size_t()
+    arr = make_params(dict(nx=16, ny=16, nz=16))
+    arr[0].shared_fluid = 1                  # nothing before the first entry
+    assert L.lbm_workspace_bytes(arr, 1, 1, C.byref(n)) == capi.LBM_EINVAL
+    arr = make_params(_group())
+    arr[1].shared_fluid = 2
+    assert L.lbm_workspace_bytes(arr, 2, 1, C.byref(n)) == capi.LBM_EINVAL
+    # 16 spheres per fluid at most: 17 spheres spaced 12 apart in a long duct
+    many = dict(nx=16, ny=16, nz=12 * 17, walls=3, radius=2.5, X0=(7.5, 7.5, 6.0),
+                spheres=[dict(radius=2.5, X0=(7.5, 7.5, 6.0 + 12 * k)) for k in range(1, 17)])
+    with pytest.raises(capi.LbmError) as e:
+        _bytes(capi, many, "fp32")
+    assert e.value.code == capi.LBM_EINVAL and b"more than 16" in str(e.value).encode()
+    many["spheres"] = many["spheres"][:15]
+    assert _bytes(capi, many, "fp32") > 0
