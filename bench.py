@@ -167,10 +167,17 @@ def forms_comparison(torch, steps_single=2000, steps_ensemble=200, steps_adjoint
     sim = make_sim(torch, reps, prec, tune_steps=50)
     el, _, _ = timed_steps(torch, sim, steps_ensemble, 20, every=0)
     ens = nodes_of(reps) * steps_ensemble / el / 1e6
+    # the same steps replayed as HIP graphs of 50 steps (one graph launch per
+    # 50 steps of every replica); the first replay instantiates the graph
+    sim.set_graph(50)
+    el_g, _, _ = timed_steps(torch, sim, steps_ensemble, 50, every=0)
+    ens_g = nodes_of(reps) * steps_ensemble / el_g / 1e6
     sim.close()
     del sim
     out["ensemble"] = {"workload": desc, "MLUPS": round(ens, 1), "steps": steps_ensemble,
-                       "vs_plain": round(ens / plain, 3)}
+                       "vs_plain": round(ens / plain, 3),
+                       "graph": {"steps_per_graph": 50, "MLUPS": round(ens_g, 1),
+                                 "vs_plain_launches": round(ens_g / ens, 3)}}
     from paper_1909_01092_amd import workloads as w
     p = w.ADJOINT
     sim = make_sim(torch, [p], "fp32", tune_steps=100)

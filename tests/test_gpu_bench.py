@@ -72,4 +72,6 @@ def test_default_bench_line_large_channel_and_forms():
         assert v["peak"] == 614.4 and 0.0 < v["frac"] < 1.0 and 0.0 < v["busy"] < 1.0
     f = d["forms"]
     assert f["plain"]["MLUPS"] > 0 and f["ensemble"]["vs_plain"] > 0 and f["adjoint"]["cost_vs_plain"] > 1.0
+    gr = f["ensemble"]["graph"]
+    assert gr["steps_per_graph"] == 50 and gr["MLUPS"] > 0 and gr["vs_plain_launches"] > 0
     print(json.dumps({"roofline": ro, "valu": d["valu"], "forms": f}), flush=True)
