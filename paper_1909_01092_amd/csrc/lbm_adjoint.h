@@ -64,13 +64,15 @@ struct AdjArgs {
     double *vtb;             // box: adjoint of the wetting-layer densities [2][S^3]
     double *ubn;             // box: uncovered-node density adjoint per kept neighbour [2][S^3]
     void *nfw;               // box: NodeFwd<T> of the nodes with sphere links [S^3]
-    double *partA;           // [nwg][ADJ_PA]
+    double *partA;           // [nlt][ADJ_PA]
     double *partB;           // [nwg][ADJ_PB]
     double *partE;           // [nbw][PART] event partials
     double *partC;           // [nbw][PART] wetting-chain partials
     double *partL;           // [2 nbw][PART] link partials (same slots as partA)
     double *partM;           // [nmw][PART] wall-mirror partials
-    int32_t nwg;             // workgroups of the node kernels (256 threads, one node each)
+    int32_t nwg;             // workgroups of the gather kernel (256 threads, one node each)
+    int32_t lty, nlt;        // local kernel: tile rows (of one plane), tiles (one workgroup each)
+    int32_t desc_nx;         // nodes per x-row (host copy, for the local kernel's LDS size)
     int32_t nbw;             // workgroups of the box kernels (256 threads, one box node each)
     int32_t nmw;             // workgroups of the wall-face kernel (256 threads, one face node each)
 };

@@ -316,12 +316,14 @@ __global__ __launch_bounds__(NB) void k_adj_kept(AdjArgs a) {
 // by the force), velocity and species-momentum noise as the main kernel
 // forms them; plus which links leave through a wall or into the sphere.
 
-template <typename T>
+// nbr(i, rt) gives the densities the force reads at the neighbour along c_i
+// (wrapped on periodic axes, clamped onto the lattice across a wall; the
+// wetting layer's on particle nodes).
+template <typename T, typename NbrRt>
 __device__ __forceinline__ void node_forward(const AdjArgs &a, const RepDesc &D, const RepState &sn,
                                              const Geo &g, const int (&p)[3], int64_t n, bool near,
-                                             const Coef<T> &cf, NodeFwd<T> &f) {
+                                             const Coef<T> &cf, NodeFwd<T> &f, NbrRt &&nbr) {
     const int64_t N = g.N;
-    const int S3 = D.S * D.S * D.S;
     const T *rec = static_cast<const T *>(a.recn);
     for (int l = 0; l < 2; l++) {
         f.rd[l] = rec[l * N + n];
@@ -349,15 +351,8 @@ __device__ __forceinline__ void node_forward(const AdjArgs &a, const RepDesc &D,
         }
         int bm = -1;
         const bool ms = near && solid_at(m3[0], m3[1], m3[2], D, sn.org, sn.X, g, bm);
-        const int64_t mi = lin(m3, g);
         T rt[2];
-        if (ms) {
-            rt[0] = T(a.vt[bm] - D.rho0[0]);
-            rt[1] = T(a.vt[S3 + bm] - D.rho0[1]);
-        } else {
-            rt[0] = rec[mi];
-            rt[1] = rec[N + mi];
-        }
+        nbr(i, rt);
         const T w = T(wgt(i));
         for (int l = 0; l < 2; l++)
             for (int q = 0; q < 3; q++)
@@ -472,49 +467,90 @@ __device__ __forceinline__ void node_finish(const NodeFwd<T> &f, const RepDesc &
 }
 
 // ============================================================ k_adj_local
-// One thread per node, fluid at X^n: the adjoint of f*_i(x) from where
-// streaming took it (a neighbour's Abar; the node's own reflected Abar for
-// links through a wall or into the sphere, whose moving-wall terms
-// k_adj_links adds), then the collision and node-local force adjoints.
-// FP32: held to 128 VGPRs (four waves per SIMD; a few values spill), which
-// hides more of the gathers' latency than the unconstrained 132.
+// Tile = ty full x-rows of one plane z.  The densities the force reads
+// (recorded, or the wetting layer's on particle nodes) and the adjoint state
+// after the step (8 values) of the tile plus a one-node halo (rows y0-1 and
+// y0+rows, planes z-1 and z+1; mirrored across walls, wrapped on periodic
+// axes) are staged in LDS, so a node's 18-neighbour gathers read LDS.  Per
+// fluid node: the adjoint of f*_i(x) from where streaming took it (a
+// neighbour's Abar; the node's own reflected Abar for links through a wall
+// or into the sphere, whose moving-wall terms k_adj_links adds), then the
+// collision and node-local force adjoints.
+// FP32: held to 128 VGPRs (four waves per SIMD).
+constexpr int LV = 10;  // staged values per node: rt_A, rt_B, Abar_rho_A, Abar_rho_B, Abar_j_A (3), Abar_j_B (3)
+
 template <typename T>
 __global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adj_local(AdjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[(NB / 64) * ADJ_PA];
+    T *lds = reinterpret_cast<T *>(smem);
     const RepDesc D = a.desc[0];
     const RepState sn = *a.stn;
     const Geo g = geo_of(D);
     const int64_t N = g.N;
-    const int64_t n = (int64_t)blockIdx.x * NB + threadIdx.x;
+    const int nx = g.nx, ty = a.lty, nty = (g.ny + ty - 1) / ty;
+    const int yt = blockIdx.x % nty, z = blockIdx.x / nty;
+    const int y0 = yt * ty, rows = min(ty, g.ny - y0);
+    const int t = threadIdx.x, nin = nx * rows;
+    const bool inner = t < nin;
+    const int x = inner ? t % nx : 0, yl = inner ? t / nx : 0, y = y0 + yl;
+    const int pr = (ty + 2) * nx;  // LDS elements per plane and staged value
+    const T *rec = static_cast<const T *>(a.recn);
+    const T *A1 = static_cast<const T *>(a.Anext);
+    // slot dz + 1 holds plane z + dz
+    auto L = [&](int dz, int v, int row, int xx) -> T & {
+        return lds[((dz + 1) * LV + v) * pr + (row + 1) * nx + xx];
+    };
+    {
+        // stage planes z - 1, z, z + 1: rows -1 .. rows of the tile, every x
+        const int S3 = D.S * D.S * D.S;
+        const int per = (rows + 2) * nx;
+        for (int e = t; e < 3 * per; e += NB) {
+            const int dz = e / per - 1, r = e % per;
+            const int row = r / nx - 1, xx = r % nx;
+            const int q[3] = {xx, mirror1(y0 + row, g.ny, g.wy), mirror1(z + dz, g.nz, g.wz)};
+            const int64_t m = lin(q, g);
+            int bm = -1;
+            const bool ms = near_box(q, D, sn.org, g) && solid_at(q[0], q[1], q[2], D, sn.org, sn.X, g, bm);
+            L(dz, 0, row, xx) = ms ? T(a.vt[bm] - D.rho0[0]) : rec[m];
+            L(dz, 1, row, xx) = ms ? T(a.vt[S3 + bm] - D.rho0[1]) : rec[N + m];
+#pragma unroll
+            for (int k = 0; k < 8; k++) L(dz, 2 + k, row, xx) = A1[k * N + m];
+        }
+    }
+    __syncthreads();
     double acc[ADJ_PA];
 #pragma unroll
     for (int k = 0; k < ADJ_PA; k++) acc[k] = 0.0;
-    const T *A1 = static_cast<const T *>(a.Anext);
     T *A0 = static_cast<T *>(a.Acur);
     T *Fo = static_cast<T *>(a.Fb);
+    const int p[3] = {x, y, z};
+    const int64_t n = lin(p, g);
     int bs = -1;
-    const bool live = n < N;
-    const int p[3] = {(int)(n % g.nx), (int)((n / g.nx) % g.ny), (int)(n / ((int64_t)g.nx * g.ny))};
-    const bool near = live && near_box(p, D, sn.org, g);
-    const bool solid = near && solid_at(p[0], p[1], p[2], D, sn.org, sn.X, g, bs);
-    if (live && solid) {
+    const bool near = inner && near_box(p, D, sn.org, g);
+    const bool solid = near && solid_at(x, y, z, D, sn.org, sn.X, g, bs);
+    if (inner && solid) {
         for (int k = 0; k < 8; k++) A0[k * N + n] = T(0);
         for (int k = 0; k < 6; k++) Fo[k * N + n] = T(0);
     }
-    if (live && !solid) {
+    if (inner && !solid) {
+        const int xm = mirror1(x - 1, nx, g.wx), xp = mirror1(x + 1, nx, g.wx);
         const Coef<T> cf = make_coef_dev<T>(D);
         NodeFwd<T> f;
-        node_forward(a, D, sn, g, p, n, near, cf, f);
-        if (f.link) static_cast<NodeFwd<T> *>(a.nfw)[bbox_index(p[0], p[1], p[2], sn.org, D.S, g)] = f;
+        node_forward(a, D, sn, g, p, n, near, cf, f, [&](int i, T (&rt)[2]) {
+            const int xx = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+            rt[0] = L(cz(i), 0, yl + cy(i), xx);
+            rt[1] = L(cz(i), 1, yl + cy(i), xx);
+        });
+        if (f.link) static_cast<NodeFwd<T> *>(a.nfw)[bbox_index(x, y, z, sn.org, D.S, g)] = f;
         T rb[2], Fbv[2][3];
         T ub[3] = {T(0), T(0), T(0)}, xb[3] = {T(0), T(0), T(0)};
 #pragma unroll 1
         for (int l = 0; l < 2; l++) {
             T zl[16];
             comp_noise(D, sn, n, l, cf, zl);
-            const T *Ab = A1 + (int64_t)(2 + 3 * l) * N;
-            const T Ar = A1[l * N + n];
-            const T Aj[3] = {Ab[n], Ab[N + n], Ab[2 * N + n]};
+            const T Ar = L(0, 2 + l, yl, x);
+            const T Aj[3] = {L(0, 4 + 3 * l, yl, x), L(0, 5 + 3 * l, yl, x), L(0, 6 + 3 * l, yl, x)};
             T fpb[Q];
             fpb[0] = Ar;
 #pragma unroll
@@ -523,13 +559,12 @@ __global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                     fpb[i] = Ar - (T(cx(i)) * Aj[0] + T(cy(i)) * Aj[1] + T(cz(i)) * Aj[2]);
                     continue;
                 }
-                int q3[3];
-                step_in(p, i, g, q3);
-                const int64_t tg = lin(q3, g);
-                T v = A1[l * N + tg];
-                if (cx(i)) v += cx(i) > 0 ? Ab[tg] : -Ab[tg];
-                if (cy(i)) v += cy(i) > 0 ? Ab[N + tg] : -Ab[N + tg];
-                if (cz(i)) v += cz(i) > 0 ? Ab[2 * N + tg] : -Ab[2 * N + tg];
+                const int xx = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+                const int rt = yl + cy(i);
+                T v = L(cz(i), 2 + l, rt, xx);
+                if (cx(i)) v += cx(i) > 0 ? L(cz(i), 4 + 3 * l, rt, xx) : -L(cz(i), 4 + 3 * l, rt, xx);
+                if (cy(i)) v += cy(i) > 0 ? L(cz(i), 5 + 3 * l, rt, xx) : -L(cz(i), 5 + 3 * l, rt, xx);
+                if (cz(i)) v += cz(i) > 0 ? L(cz(i), 6 + 3 * l, rt, xx) : -L(cz(i), 6 + 3 * l, rt, xx);
                 fpb[i] = v;
             }
             T rbl, Fbl[3];
@@ -895,10 +930,10 @@ __device__ __forceinline__ void adj_sums(const AdjArgs &a, double *red) {
     double acc[18];
 #pragma unroll
     for (int k = 0; k < 18; k++) acc[k] = 0.0;
-    for (int w = t; w < a.nwg; w += NB) {
+    for (int w = t; w < a.nlt; w += NB)
         for (int k = 0; k < ADJ_PA; k++) acc[k] += a.partA[(int64_t)w * ADJ_PA + k];
+    for (int w = t; w < a.nwg; w += NB)
         for (int k = 0; k < ADJ_PB; k++) acc[ADJ_PA + k] += a.partB[(int64_t)w * ADJ_PB + k];
-    }
     for (int w = t; w < a.nmw; w += NB)
         for (int k = 0; k < 2; k++) acc[15 + k] += a.partM[(int64_t)w * PART + k];
     for (int w = t; w < 2 * a.nbw; w += NB)
@@ -995,7 +1030,8 @@ hipError_t launch_step_t(const AdjArgs &a, hipStream_t s, hipEvent_t e0, hipEven
         const hipError_t e = hipEventRecord(e0, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_adj_local<T>), dim3(a.nwg), dim3(NB), 0, s, a);
+    const size_t lds = (size_t)3 * LV * (a.lty + 2) * a.desc_nx * sizeof(T);
+    hipLaunchKernelGGL((k_adj_local<T>), dim3(a.nlt), dim3(NB), lds, s, a);
     if (e1) {
         const hipError_t e = hipEventRecord(e1, s);
         if (e != hipSuccess) return e;

@@ -478,8 +478,17 @@ int read_state(lbm_ctx *c, int r, RepState *s) {
 // the start of every segment and after the last step, the moments and states
 // recorded while a segment is replayed, two adjoint states of 8 values per
 // node, the node-force adjoint, bounding-box arrays and partial sums.
+// rows per tile of the adjoint's node kernel (one plane per tile) and its
+// LDS bytes (10 staged values over the tile rows plus a one-row halo on each
+// side, on the tile's plane and the planes above and below)
+constexpr size_t ADJ_LDS_MAX = 160 * 1024;
+int adj_tile_rows(const lbm_params &q) { return std::max(1, std::min(q.ny, 256 / q.nx)); }
+size_t adj_lds_bytes(const lbm_params &q, int prec) {
+    return (size_t)3 * 10 * (adj_tile_rows(q) + 2) * q.nx * (prec == LBM_FP64 ? 8 : 4);
+}
+
 struct AdjLayout {
-    int nseg = 0, seg = 0, nwg = 0, nbw = 0, nmw = 0;
+    int nseg = 0, seg = 0, nwg = 0, nbw = 0, nmw = 0, lty = 0, nlt = 0;
     size_t ckb = 0, recb = 0, Ab = 0;
     size_t ck = 0, rec = 0, rst = 0, A[2] = {0, 0}, Fb = 0, vt = 0, vinv = 0, vtb = 0, ubn = 0, nfw = 0,
            partA = 0, partB = 0, partE = 0, partC = 0, partL = 0, partM = 0, adj = 0, total = 0;
@@ -492,6 +501,9 @@ int adj_check(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     if (!c->desc[0].has_particle) return fail(c, LBM_EINVAL, "the adjoint needs a sphere (radius > 0)");
     if (nsteps < 1) return fail(c, LBM_EINVAL, "nsteps must be >= 1");
     if (segment < 0) return fail(c, LBM_EINVAL, "segment must be >= 0 (0: 50 steps)");
+    if (adj_lds_bytes(c->p[0], c->prec) > ADJ_LDS_MAX)
+        return fail(c, LBM_EINVAL, "x-rows too long for the adjoint's LDS tiles at this precision "
+                                   "(FP64: nx <= 227)");
     return LBM_OK;
 }
 
@@ -504,6 +516,12 @@ AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     const int64_t S3 = c->L.S3tot;
     A.nwg = (int)((N + 255) / 256);
     A.nbw = (int)((S3 + 255) / 256);
+    {
+        // node-kernel tiles: ty full x-rows of one plane
+        const lbm_params &q = c->p[0];
+        A.lty = adj_tile_rows(q);
+        A.nlt = (int)((int64_t)((q.ny + A.lty - 1) / A.lty) * q.nz);
+    }
     {
         const lbm_params &q = c->p[0];
         const int64_t nn[3] = {q.nx, q.ny, q.nz};
@@ -529,7 +547,7 @@ AdjLayout adj_plan(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     A.vtb = take(sizeof(double) * 2 * S3);
     A.ubn = take(sizeof(double) * 2 * S3);
     A.nfw = take(NODE_FWD_BYTES * S3);
-    A.partA = take(sizeof(double) * ADJ_PA * A.nwg);
+    A.partA = take(sizeof(double) * ADJ_PA * A.nlt);
     A.partB = take(sizeof(double) * ADJ_PB * A.nwg);
     A.partE = take(sizeof(double) * PART * A.nbw);
     A.partC = take(sizeof(double) * PART * A.nbw);
@@ -1260,6 +1278,9 @@ int adjoint_backward(lbm_ctx *c, double grad[5], double *J) {
     aa.partL = reinterpret_cast<double *>(w + A.partL);
     aa.partM = reinterpret_cast<double *>(w + A.partM);
     aa.nwg = A.nwg;
+    aa.lty = A.lty;
+    aa.nlt = A.nlt;
+    aa.desc_nx = q.nx;
     aa.nbw = A.nbw;
     aa.nmw = A.nmw;
     int an = 0;  // buffer holding the adjoint of the state after the step being reversed

@@ -114,6 +114,13 @@ def test_adjoint_rejects_unsupported(Sim):
     sim = Sim([EVENTS, EVENTS], "fp64")
     with pytest.raises(LbmError):
         sim.adjoint(3)
+    # FP64 rows longer than the node kernel's LDS tiles hold
+    wide = workloads.full(dict(nx=240, ny=12, nz=12, walls=3, radius=3.0, X0=(120.2, 5.6, 5.4)))
+    sim = Sim(wide, "fp64")
+    with pytest.raises(LbmError) as e:
+        sim.adjoint(3)
+    assert b"x-rows" in str(e.value).encode()
+    Sim(wide, "fp32").adjoint(3)
 
 
 def _J_forward(Sim, p, steps, prec="fp64"):
