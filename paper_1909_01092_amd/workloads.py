@@ -143,7 +143,7 @@ def wetting(drhos=WETTING_DRHO, n: int = WETTING_N, radius: float = WETTING_R,
 
 # the paper's three particle wettabilities (Sec. 3: theta_A = 120.5, 90 and 55
 # degrees) as wetting offsets for an R = 8 sphere, read off the contact-angle
-# sweep above (bench.py --study wetting)
+# sweep above (python -m paper_1909_01092_amd.studies wetting)
 PAPER_WETTING_DRHO = {"hydrophobic": -0.146, "neutral": 0.0, "hydrophilic": 0.167}
 INTERFACE_FORCES = (0.0, 0.5, 1.0, 2.0, 3.0)
 
