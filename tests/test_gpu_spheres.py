@@ -16,7 +16,7 @@ import pytest
 
 from oracle.oracle import OracleSim
 
-from test_gpu_parity import W, dev, rel, solid_mask  # noqa: E402
+from test_gpu_parity import dev, rel, solid_mask  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
