@@ -281,8 +281,8 @@ int lbm_step_bytes(lbm_ctx *c, double *bytes);
  * Arithmetic: FP64 for LBM_FP64 contexts, FP32 node adjoints otherwise; the
  * sphere and parameter adjoints are always FP64.
  * Requirements (else LBM_EINVAL): one replica, every relaxation time 1, a
- * sphere, and (FP64 contexts) nx <= 227: the node kernel stages a tile of
- * full x-rows over three planes in at most 160 KiB of LDS.  dev_adj: caller-owned device buffer, 256-byte aligned, of at
+ * sphere, and (FP64 contexts) nx <= 226: the node kernel stages a tile of
+ * full x-rows over three planes in the 160 KiB of LDS a workgroup can hold.  dev_adj: caller-owned device buffer, 256-byte aligned, of at
  * least lbm_adjoint_bytes(c, nsteps, segment) bytes (LBM_ENOMEM otherwise);
  * the library keeps no reference to it after the call.  On success the
  * context holds the state after the nsteps steps, as lbm_step(c, nsteps)

@@ -480,8 +480,10 @@ int read_state(lbm_ctx *c, int r, RepState *s) {
 // node, the node-force adjoint, bounding-box arrays and partial sums.
 // rows per tile of the adjoint's node kernel (one plane per tile) and its
 // LDS bytes (10 staged values over the tile rows plus a one-row halo on each
-// side, on the tile's plane and the planes above and below)
-constexpr size_t ADJ_LDS_MAX = 160 * 1024;
+// side, on the tile's plane and the planes above and below).  A workgroup
+// holds at most 160 KiB of LDS on gfx950; 1 KiB of it is left for the
+// kernel's static reduction array (416 bytes).
+constexpr size_t ADJ_LDS_MAX = 160 * 1024 - 1024;
 int adj_tile_rows(const lbm_params &q) { return std::max(1, std::min(q.ny, 256 / q.nx)); }
 size_t adj_lds_bytes(const lbm_params &q, int prec) {
     return (size_t)3 * 10 * (adj_tile_rows(q) + 2) * q.nx * (prec == LBM_FP64 ? 8 : 4);
@@ -503,7 +505,7 @@ int adj_check(lbm_ctx *c, int32_t nsteps, int32_t segment) {
     if (segment < 0) return fail(c, LBM_EINVAL, "segment must be >= 0 (0: 50 steps)");
     if (adj_lds_bytes(c->p[0], c->prec) > ADJ_LDS_MAX)
         return fail(c, LBM_EINVAL, "x-rows too long for the adjoint's LDS tiles at this precision "
-                                   "(FP64: nx <= 227)");
+                                   "(FP64: nx <= 226)");
     return LBM_OK;
 }
 
