@@ -247,6 +247,7 @@ struct lbm_ctx {
     size_t lds = 0;
     int cur = 0;
     int tau1 = 0;
+    int noise = 0;            // some replica has kT > 0
     int groups = 0;           // some fluid holds several spheres
     int graph_steps = 0, graph_parity = -1;
     hipGraphExec_t gexec = nullptr;
@@ -403,6 +404,7 @@ int enqueue_step(lbm_ctx *c, bool timed, const StepScratch &sc) {
     m.vrho = c->d_vrho();
     m.rho_n = sc.rho_n;
     m.tau1 = c->tau1;
+    m.noise = c->noise;
     m.groups = c->groups;
     if (timed && c->ev_used + 2 > c->ev.size()) {
         for (int k = 0; k < 256; k++) {
@@ -634,6 +636,7 @@ LBM_API int lbm_init(const lbm_params *p_in, int32_t n_replicas, int32_t precisi
         for (double t : D.tau)
             if (t != 1.0) c->tau1 = 0;
         D.kT = q.kT;
+        if (q.kT > 0.0) c->noise = 1;
         D.init_amp = q.init_amp;
         D.init_split = q.init_split;
         // rows of at most two cache lines (padded): their x-ghost elements sit in

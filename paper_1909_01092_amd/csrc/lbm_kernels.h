@@ -19,6 +19,7 @@ struct MainArgs {
     double *rho_n;             // densities of step n near the sphere (bbox), written
     int32_t tau1;              // every relaxation time of every replica is 1
     int32_t groups;            // some fluid holds several spheres
+    int32_t noise;             // some replica has kT > 0
 };
 
 struct LinkArgs {

@@ -328,7 +328,11 @@ constexpr bool main_unroll = sizeof(T) == 4 && TAU1;
 
 // GROUP: fluids may hold several spheres (their boxes are searched too); a
 // separate instantiation, so the single-sphere form keeps its registers.
-template <typename S, typename T, int B, bool TAU1, bool GROUP>
+// NOISE: some replica of the launch has kT > 0.  Every node then draws its
+// normals; a replica with kT = 0 has zero amplitudes and takes none of them
+// (products with zero).  Without it no normals are drawn.  Being a compile-
+// time choice, the noise-free form costs the noisy one nothing.
+template <typename S, typename T, int B, bool TAU1, bool GROUP, bool NOISE>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(main_fast_form<S, T, TAU1> ? 4 : 1)))
 void k_main(MainArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -522,7 +526,7 @@ void k_main(MainArgs a) {
             const uint32_t node = (uint32_t)(x + nx * (y + g.ny * z));
             T u[3], xid[3];
             T zz[36];
-            if (cf.noise) noise_block<T>(node, step, 8u, k0, k1, zz + 32);
+            if constexpr (NOISE) noise_block<T>(node, step, 8u, k0, k1, zz + 32);
             else zz[32] = zz[33] = zz[34] = T(0);
             common_velocity(rd, j, F, zz, cf, u, xid);
             const bool zlo = z == 0, zhi = z == g.nz - 1;
@@ -538,7 +542,7 @@ void k_main(MainArgs a) {
                 const T r0l = l ? cf.rho0[1] : cf.rho0[0];
                 const T sig = l ? T(-1) : T(1);
                 T zl[16];
-                if (cf.noise) {
+                if constexpr (NOISE) {
 #pragma unroll
                     for (int b = 0; b < 4; b++)
                         noise_block<T>(node, step, (uint32_t)(4 * l + b), k0, k1, zl + 4 * b);
@@ -1506,8 +1510,13 @@ __global__ __launch_bounds__(256) void k_fields_a(FieldArgs a) {
 // ============================================================== launchers
 template <typename S, typename T, int B, bool GROUP>
 void launch_main_b(const MainArgs &a, int grid, size_t lds, hipStream_t s) {
-    if (a.tau1) hipLaunchKernelGGL((k_main<S, T, B, true, GROUP>), dim3(grid), dim3(B), lds, s, a);
-    else hipLaunchKernelGGL((k_main<S, T, B, false, GROUP>), dim3(grid), dim3(B), lds, s, a);
+    if (a.tau1) {
+        if (a.noise) hipLaunchKernelGGL((k_main<S, T, B, true, GROUP, true>), dim3(grid), dim3(B), lds, s, a);
+        else hipLaunchKernelGGL((k_main<S, T, B, true, GROUP, false>), dim3(grid), dim3(B), lds, s, a);
+    } else {
+        if (a.noise) hipLaunchKernelGGL((k_main<S, T, B, false, GROUP, true>), dim3(grid), dim3(B), lds, s, a);
+        else hipLaunchKernelGGL((k_main<S, T, B, false, GROUP, false>), dim3(grid), dim3(B), lds, s, a);
+    }
 }
 
 template <typename S, typename T, bool GROUP>

@@ -281,6 +281,30 @@ def test_ensemble_of_uneven_replicas(Sim):
         compare(sim, r, 1e-12, rep=k, what=f"ensemble replica {k}")
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_noise_free_replica_among_noisy_ones(Sim, prec, tol):
+    """A kT = 0 replica launched with noisy ones runs the noisy kernel form
+    with zero amplitudes: it matches the oracle, and equals (as numbers; only
+    the sign of an exact zero may differ) the same replica run alone, which
+    takes the noise-free form."""
+    quiet = workloads.channel(16, 24, kT=0.0, radius=3.0, g=(0, 0, 5e-5), seed=7, replica=1,
+                              U0=(0.0, 0.01, 0.05))
+    reps = [workloads.channel(14, 20, kT=1e-5, radius=2.5, g=(0, 0, 5e-5), seed=7, replica=0), quiet,
+            workloads.full(dict(nx=12, ny=10, nz=18, walls=3, kT=1e-4, init_amp=1e-3, G=1.5,
+                                seed=7, replica=2))]
+    sim, alone = Sim(reps, prec), Sim(quiet, prec)
+    refs = [OracleSim(q) for q in reps]
+    sim.step(30)
+    alone.step(30)
+    for k, r in enumerate(refs):
+        r.step(30)
+        compare(sim, r, tol, rep=k, what=f"{prec} mixed-noise replica {k}")
+    assert np.array_equal(sim.populations(1), alone.populations(0))
+    pm, pa = sim.particle_state(1), alone.particle_state(0)
+    for key in ("X", "U", "W", "F", "T"):
+        assert np.array_equal(pm[key], pa[key]), key
+
+
 def test_timing_samples_every_kth_step(Sim):
     from paper_1909_01092_amd._capi import LbmError
     sim = Sim(workloads.channel(16, 24, kT=1e-5, radius=3.0, g=(0, 0, 5e-5)), "fp32")
