@@ -155,6 +155,31 @@ def test_fp32_parity_single_run_slice(Sim):
     assert errU < 1e-5
 
 
+def test_fp32_parity_single_run_full_size(Sim):
+    """The whole single-run channel, 64 x 64 x 256 (R = 8, kT = 1e-5,
+    g = 1e-4), in the benchmark's launch shape (1024 x 4): 200 FP32 steps
+    against the oracle, every population compared (about half a minute of
+    oracle time on 16 threads)."""
+    import time
+    p = workloads.SINGLE_RUN
+    sim, ref = Sim(p, "fp32"), OracleSim(p)
+    sim.set_launch(1024, 4)
+    sim.step(200)
+    t0 = time.perf_counter()
+    ref.step(200)
+    print(f"oracle: 200 steps of 64x64x256 in {time.perf_counter() - t0:.1f} s", flush=True)
+    compare(sim, ref, 1e-6, 1e-5, what="64x64x256 single run, fp32 200 steps")
+    pg, po = sim.particle_state(), ref.particle()
+    assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    # the position to FP32's relative bar on the distance travelled (about
+    # 0.4 lattice units here): its error is the sum of the velocity errors
+    moved = np.asarray(po["X"]) - np.asarray(p["X0"])
+    errX = np.abs(pg["X"] - po["X"]).max() / np.abs(moved).max()
+    print(f"single run particle U rel err {errU:.3e}, displacement rel err {errX:.3e}", flush=True)
+    assert errU < 1e-5 and errX < 1e-5
+
+
 # distinct relaxation times per mode group (shear, bulk, momentum, ghost),
 # the brute-force pin's set: the general MRT collision of Sec. 2
 MRT_TAUS = dict(tau_shear=0.8, tau_bulk=1.1, tau_mom=0.9, tau_ghost=1.3)
