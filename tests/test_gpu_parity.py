@@ -506,6 +506,40 @@ def test_ensemble_full_size_one_step_fp32(Sim):
         compare(sim, ref, 1e-7, 2e-5, rep=r, what=f"ensemble replica {r} one step from the GPU state")
 
 
+def test_ensemble_full_size_200_steps_fp32(Sim):
+    """The full 192-replica ensemble in FP32 and in the benchmark's launch
+    shape (512 x 8), 200 steps from the initial state; the first replica of
+    each size (32 x 32 x 128, 24 x 24 x 96, 48 x 48 x 192) against the oracle
+    run alone over the same 200 steps."""
+    reps = workloads.ensemble(steps_cap=256)
+    sim = Sim(reps, "fp32")
+    sim.set_launch(512, 8)
+    sim.step(200)
+    for r in (0, 128, 160):
+        ref = OracleSim(reps[r])
+        ref.step(200)
+        compare(sim, ref, 1e-6, 1e-5, rep=r, what=f"ensemble replica {r}, 200 steps")
+        pg, po = sim.particle_state(r), ref.particle()
+        assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
+        errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+        print(f"ensemble replica {r}: particle U rel err {errU:.3e}", flush=True)
+        assert errU < 1e-5
+
+
+def test_adjoint_channel_200_steps_fp32(Sim):
+    """The adjoint form's channel, 48 x 48 x 192 (R = 6, kT = 1e-5,
+    g = 5e-5), 200 plain FP32 steps against the oracle."""
+    p = workloads.ADJOINT
+    sim, ref = Sim(p, "fp32"), OracleSim(p)
+    sim.step(200)
+    ref.step(200)
+    compare(sim, ref, 1e-6, 1e-5, what="48x48x192 adjoint channel, fp32 200 steps")
+    pg, po = sim.particle_state(), ref.particle()
+    errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+    print(f"adjoint channel particle U rel err {errU:.3e}", flush=True)
+    assert errU < 1e-5
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_no_unwritten_memory_is_read(Sim, prec):
     """Every slot a step pulls from has been written: with the workspace
