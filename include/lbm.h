@@ -312,7 +312,7 @@ int lbm_adjoint_forward(lbm_ctx *c, int32_t nsteps, int32_t segment, void *dev_a
 int lbm_adjoint_backward(lbm_ctx *c, double grad[5]);
 
 void lbm_destroy(lbm_ctx *c);
-const char *lbm_last_error(const lbm_ctx *c);  /* NULL ctx: last lbm_init error */
+const char *lbm_last_error(const lbm_ctx *c);  /* NULL ctx: the calling thread's last error of a call with no context (lbm_init, lbm_workspace_bytes) */
 
 #ifdef __cplusplus
 }
