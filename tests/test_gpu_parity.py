@@ -371,6 +371,27 @@ def test_many_replicas_finish_apart_fp64(Sim):
             assert po["n_covered"] > 0 and po["n_uncovered"] > 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_finishing_launch_equals_last_workgroup_bitwise(Sim, prec):
+    """A replica stepped alone (its step finished by the last particle
+    workgroup) and as the first of forty (finished by the separate finishing
+    launch, which sums the partials through LDS over a whole workgroup) in the
+    same launch shape: the same sums in the same order, so bit for bit the
+    same populations and sphere state, through cover / uncover events."""
+    reps = [workloads.channel(12, 16, kT=1e-5, radius=2.5, g=(0, 0, 5e-5), seed=11, replica=k,
+                              U0=(0.0, 0.01 * (k % 3), 0.1), wet_drho=0.05 * (k % 4)) for k in range(40)]
+    alone, many = Sim(reps[:1], prec), Sim(reps, prec)
+    for s in (alone, many):
+        s.set_launch(256, 4)
+        s.step(25)
+    assert np.array_equal(alone.populations(0), many.populations(0))
+    pa, pm = alone.particle_state(0), many.particle_state(0)
+    assert pa["n_covered"] > 0 and pa["n_uncovered"] > 0
+    for key in ("X", "U", "W", "F", "T", "Pev", "Lev", "delta", "n_fluid"):
+        assert np.array_equal(pa[key], pm[key]), key
+    assert np.array_equal(alone.u_series(0), many.u_series(0))
+
+
 @pytest.mark.timeout(900)
 def test_large_full_size_one_step_fp16(Sim):
     """192 x 192 x 1024, R = 16, kT = 1e-4, FP16 relative-deviation storage in
