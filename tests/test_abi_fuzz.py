@@ -84,6 +84,15 @@ def test_workspace_bytes_accepts_or_rejects_cleanly(lib, entries, prec):
     assert prec in (0, 1, 2)
     assert arr[0].shared_fluid == 0
     for p in arr:
+        assert p.shared_fluid in (0, 1)
+        for v in (*p.X0, *p.U0, *p.W0):
+            assert math.isfinite(v)
+        if p.radius > 0:
+            assert p.rho_p > 0 and all(abs(u) < 0.5 for u in p.U0)
+        if p.shared_fluid:
+            # its fluid fields are not read: the fluid is its group's first entry's
+            assert p.radius > 0
+            continue
         assert 2 <= p.nx <= 256 and p.ny >= 2 and p.nz >= 2
         assert p.walls <= 7
         assert p.rho0[0] > 0 and p.rho0[1] > 0
@@ -91,8 +100,5 @@ def test_workspace_bytes_accepts_or_rejects_cleanly(lib, entries, prec):
             assert t > 0.5 and math.isfinite(t)
         assert p.kT >= 0 and math.isfinite(p.kT) and math.isfinite(p.G)
         assert p.force_mode in (0, 1) and p.series_cap >= 1 and 0 <= p.init_split < p.nz
-        assert p.shared_fluid in (0, 1)
-        for v in (*p.g, *p.X0, *p.U0, *p.W0):
+        for v in p.g:
             assert math.isfinite(v)
-        if p.radius > 0:
-            assert p.rho_p > 0 and all(abs(u) < 0.5 for u in p.U0)
