@@ -1,0 +1,77 @@
+"""Every form of the main kernel against the FP64 oracle: storage (FP64,
+FP32, FP16) x relaxation (every time 1, or the distinct MRT rates of Sec. 2)
+x spheres (one, or two in one fluid) x noise (kT > 0, or kT = 0), each a
+separate compiled form.  A walled 12 x 12 x 36 duct with moving spheres, 20
+steps, in the default launch shape.
+
+Bars: FP64 1e-12 on populations and deviations; FP32 1e-6 on populations and
+1e-5 on deviations; FP16 2e-4 on populations and 5e-4 on deviations, one
+unit roundoff of the stored relative deviations (2^-11), which 20 steps at
+these amplitudes stay well inside (about 4e-5 measured).  FP64 also compares
+every sphere's velocity to 1e-10 and the event counts exactly.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSim
+from test_gpu_parity import dev, rel, solid_mask  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+MRT = dict(tau_shear=0.8, tau_bulk=1.1, tau_mom=0.9, tau_ghost=1.3)
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-6, 1e-5), "fp16": (2e-4, 5e-4)}
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_01092_amd.sim import Simulation
+    return Simulation
+
+
+def duct(mrt, group, kT):
+    p = dict(nx=12, ny=12, nz=36, walls=3, init_amp=1e-3, G=1.5, kT=kT, seed=17, g=(0.0, 0.0, 1e-4),
+             radius=2.5, rho_p=2.0, wet_drho=0.1, X0=(5.6, 5.3, 8.4), U0=(0.03, -0.02, 0.05),
+             W0=(0.05, 0.02, 0.03))
+    if mrt:
+        p.update(MRT)
+    if group:
+        p["spheres"] = [dict(radius=2.2, rho_p=1.6, wet_drho=-0.15, X0=(6.2, 6.7, 26.5),
+                             U0=(-0.02, 0.03, -0.04), W0=(-0.02, 0.0, 0.01))]
+    return p
+
+
+CASES = list(itertools.product(["fp64", "fp32", "fp16"], [False, True], [False, True], [1e-4, 0.0]))
+
+
+@pytest.mark.parametrize("prec,mrt,group,kT", CASES,
+                         ids=[f"{p}-{'mrt' if m else 'tau1'}-{'group' if g else 'one'}-{'noise' if k else 'quiet'}"
+                              for p, m, g, k in CASES])
+def test_main_kernel_form_against_oracle(Sim, prec, mrt, group, kT):
+    from oracle import oracle as om
+    p = duct(mrt, group, kT)
+    q = dict(om.DEFAULTS)
+    q.update(p)
+    sim, ref = Sim(p, prec), OracleSim(q)
+    sim.step(20)
+    ref.step(20)
+    f, fr = sim.populations(0), ref.populations()
+    assert np.array_equal(solid_mask(f), solid_mask(fr))
+    rho0 = q["rho0"]
+    e, ed = rel(f, fr), rel(dev(f, rho0), dev(fr, rho0))
+    print(f"{prec} mrt={mrt} group={group} kT={kT}: rel err f {e:.3e}, deviations {ed:.3e}", flush=True)
+    tol, tol_dev = TOL[prec]
+    assert e < tol and ed < tol_dev
+    for k in range(2 if group else 1):
+        pg = sim.particle_state(k)
+        po = ref.sphere(k) if group else ref.particle()
+        assert pg["step"] == po["step"] == 20
+        assert np.all(np.isfinite(pg["U"]))
+        if prec == "fp64":
+            assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
+            errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
+            assert errU < 1e-10, (k, errU)
