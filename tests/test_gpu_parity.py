@@ -371,7 +371,7 @@ def test_many_replicas_finish_apart_fp64(Sim):
             assert po["n_covered"] > 0 and po["n_uncovered"] > 0
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_finishing_launch_equals_last_workgroup_bitwise(Sim, prec):
     """A replica stepped alone (its step finished by the last particle
     workgroup) and as the first of forty (finished by the separate finishing
