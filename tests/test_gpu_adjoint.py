@@ -58,9 +58,13 @@ def _report(what, J, grad, Jo, go):
         print(f"  grad[{k}] {grad[k]: .12e} oracle {go[k]: .12e}", flush=True)
 
 
-@pytest.mark.parametrize("case,steps", [("EVENTS", 30), ("WALLS", 40), ("PERIODIC", 30)])
+# the events case without thermal noise: the node kernels' noise-free branch
+QUIET = dict(EVENTS, kT=0.0)
+
+
+@pytest.mark.parametrize("case,steps", [("EVENTS", 30), ("WALLS", 40), ("PERIODIC", 30), ("QUIET", 30)])
 def test_adjoint_fp64_matches_oracle(Sim, case, steps):
-    p = {"EVENTS": EVENTS, "WALLS": WALLS, "PERIODIC": PERIODIC}[case]
+    p = {"EVENTS": EVENTS, "WALLS": WALLS, "PERIODIC": PERIODIC, "QUIET": QUIET}[case]
     print(f"case {case} steps {steps}", flush=True)
     Jo, go = _oracle(p, steps)
     sim = Sim(p, "fp64")
@@ -69,7 +73,7 @@ def test_adjoint_fp64_matches_oracle(Sim, case, steps):
     assert abs(J - Jo) <= 1e-12 * abs(Jo)
     for k in range(5):
         assert abs(grad[k] - go[k]) <= 1e-9 * abs(go[k]) + 1e-14, (k, grad[k], go[k])
-    if case in ("EVENTS", "PERIODIC"):
+    if case in ("EVENTS", "PERIODIC", "QUIET"):
         st = sim.particle_state()
         assert st["n_covered"] > 0 and st["n_uncovered"] > 0
     if case == "PERIODIC":
