@@ -75,3 +75,25 @@ def test_main_kernel_form_against_oracle(Sim, prec, mrt, group, kT):
             assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
             errU = np.abs(pg["U"] - po["U"]).max() / np.abs(po["U"]).max()
             assert errU < 1e-10, (k, errU)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_species_momentum_noise_off_against_oracle(Sim, prec):
+    """kT > 0 with the species-momentum (diffusive) noise switched off
+    (noise_diffusive = 0): only the stress and ghost modes are noisy."""
+    from oracle import oracle as om
+    p = dict(duct(True, False, 1e-4), noise_diffusive=0)
+    q = dict(om.DEFAULTS)
+    q.update(p)
+    sim, ref = Sim(p, prec), OracleSim(q)
+    sim.step(20)
+    ref.step(20)
+    f, fr = sim.populations(0), ref.populations()
+    e, ed = rel(f, fr), rel(dev(f, q["rho0"]), dev(fr, q["rho0"]))
+    print(f"{prec} without species-momentum noise: rel err f {e:.3e}, deviations {ed:.3e}", flush=True)
+    tol, tol_dev = TOL[prec]
+    assert e < tol and ed < tol_dev
+    # and the switch matters: the same run with it on differs
+    on = Sim(duct(True, False, 1e-4), prec)
+    on.step(20)
+    assert not np.array_equal(on.populations(0), f)
