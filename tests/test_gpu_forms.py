@@ -97,3 +97,27 @@ def test_species_momentum_noise_off_against_oracle(Sim, prec):
     on = Sim(duct(True, False, 1e-4), prec)
     on.step(20)
     assert not np.array_equal(on.populations(0), f)
+
+
+@pytest.mark.parametrize("walls", [1, 2, 4, 5, 6])
+def test_every_wall_mask_against_oracle(Sim, walls):
+    """Walls on any subset of the axes (the others periodic), where links
+    leaving the box bounce back on some faces and wrap on others, with a
+    moving sphere: FP64 against the oracle."""
+    from oracle import oracle as om
+    p = dict(nx=14, ny=14, nz=20, walls=walls, init_amp=1e-3, G=1.5, kT=1e-4, seed=23, g=(2e-5, -1e-5, 1e-4),
+             radius=2.5, rho_p=2.0, wet_drho=0.1, X0=(6.6, 7.3, 9.4), U0=(0.03, -0.02, 0.05),
+             W0=(0.02, 0.01, -0.03), **MRT)
+    q = dict(om.DEFAULTS)
+    q.update(p)
+    sim, ref = Sim(p, "fp64"), OracleSim(q)
+    sim.step(25)
+    ref.step(25)
+    f, fr = sim.populations(0), ref.populations()
+    assert np.array_equal(solid_mask(f), solid_mask(fr))
+    e, ed = rel(f, fr), rel(dev(f, q["rho0"]), dev(fr, q["rho0"]))
+    print(f"walls={walls}: rel err f {e:.3e}, deviations {ed:.3e}", flush=True)
+    assert e < 1e-12 and ed < 1e-12
+    pg, po = sim.particle_state(), ref.particle()
+    assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
+    assert np.abs(pg["U"] - po["U"]).max() <= 1e-10 * np.abs(po["U"]).max()
