@@ -121,3 +121,23 @@ def test_every_wall_mask_against_oracle(Sim, walls):
     pg, po = sim.particle_state(), ref.particle()
     assert (pg["n_covered"], pg["n_uncovered"]) == (po["n_covered"], po["n_uncovered"])
     assert np.abs(pg["U"] - po["U"]).max() <= 1e-10 * np.abs(po["U"]).max()
+
+
+def test_mixed_relaxation_ensemble_against_oracle(Sim):
+    """Replicas with every relaxation time 1 next to replicas with the MRT
+    rates in one context: all run the general form; each matches the oracle
+    run alone (FP64)."""
+    from oracle import oracle as om
+    reps = [dict(duct(False, False, 1e-4), replica=0), dict(duct(True, False, 1e-4), replica=1),
+            dict(duct(False, False, 0.0), replica=2, X0=(6.1, 5.9, 20.3))]
+    sim = Sim(reps, "fp64")
+    sim.step(20)
+    for k, p in enumerate(reps):
+        q = dict(om.DEFAULTS)
+        q.update(p)
+        ref = OracleSim(q)
+        ref.step(20)
+        f, fr = sim.populations(k), ref.populations()
+        e = rel(f, fr)
+        print(f"mixed relaxation, replica {k}: rel err f {e:.3e}", flush=True)
+        assert e < 1e-12
