@@ -116,11 +116,6 @@ __host__ __device__ inline void noise_block(uint32_t node, uint32_t step, uint32
     box_muller(c2, c3, z4[2], z4[3]);
 }
 
-template <typename T>
-__host__ __device__ inline void noise36(uint32_t node, uint32_t step, uint32_t k0, uint32_t k1,
-                                        T (&z)[36]) {
-    for (uint32_t b = 0; b < 9; b++) noise_block(node, step, b, k0, k1, z + 4 * b);
-}
 
 // ------------------------------------------------------------- collision
 template <typename T>
@@ -334,22 +329,6 @@ __host__ __device__ inline void relax_tau1(T rho0l, T sig, T rd, const T (&j)[3]
 #pragma unroll
     for (int k = 10; k < Q; k++) a[k] = T(inv_norm(k) * sqrt_norm(k)) * ng * zl[k - 4];
     back_transform(a, out);
-}
-
-// Collide one node, both components, in deviation variables d = f - w_i rho0_l
-// (composition of the pieces above; kernels call the pieces in their own order).
-template <typename T>
-__host__ __device__ inline void collide(const T (&d)[2][Q], const T (&F)[2][3], const T (&z)[36],
-                                        const Coef<T> &c, T (&out)[2][Q], T (&u)[3]) {
-    T rd[2], j[2][3], m[2][Q], xid[3];
-    for (int l = 0; l < 2; l++) component_modes(d[l], rd[l], j[l], m[l]);
-    common_velocity(rd, j, F, z, c, u, xid);
-    for (int l = 0; l < 2; l++) {
-        T zl[16];
-        for (int k = 0; k < 16; k++) zl[k] = z[16 * l + k];
-        relax_component(c.rho0[l], l == 0 ? T(1) : T(-1), rd[l], j[l], m[l], F[l], u, xid, zl, c,
-                        out[l]);
-    }
 }
 
 }  // namespace lbm
